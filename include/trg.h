@@ -1,0 +1,171 @@
+/*
+ * trg.h -- C ABI of the MI355X (gfx950) implementation of the coarse-graining
+ * step of ATRG and triad-ATRG for the d-dimensional Ising model.
+ *
+ * Method: Y. Sugimoto and S. Sasaki, "Triad representation for the
+ * anisotropic tensor renormalization group in four dimensions",
+ * arXiv:2507.21909.  Section, equation and appendix labels below are the
+ * paper's.
+ *
+ * Conventions shared by every entry point
+ *   - All calls return TRG_OK (0) or a negative TRG_E_* code; they never
+ *     abort or throw across the ABI.  trg_strerror() names a code,
+ *     trg_last_error() gives the message of the last failure on a state.
+ *   - A state owns every device buffer it uses; no pointer into device
+ *     memory escapes.  Host pointers passed in are only read (or written,
+ *     for outputs) during the call.
+ *   - Work is enqueued on the state's HIP stream (opt.stream, or the null
+ *     stream when NULL).  Steps are asynchronous; log_z_per_site and the
+ *     export/inspection calls synchronise the stream.  The caller keeps a
+ *     stream it passed alive until trg_destroy.
+ *   - Device: opt.device selects the GPU; the library makes it current for
+ *     the duration of each call.
+ */
+#ifndef TRG_H
+#define TRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------ */
+#define TRG_OK           0
+#define TRG_E_INVALID   -1   /* NULL pointer, D < 1, beta < 0, axis out of range, triad with dim != 4, ... */
+#define TRG_E_STATE     -2   /* step or query before tensor_init                                      */
+#define TRG_E_NOMEM     -3   /* device allocation failed or exceeds opt.workspace_cap                 */
+#define TRG_E_NUMERICAL -4   /* NaN/Inf, non-positive norm, Jacobi not converged in max_sweeps       */
+#define TRG_E_HIP       -5   /* HIP runtime error (message kept in trg_last_error)                    */
+#define TRG_E_UNSUPPORTED -6 /* a shape outside the kernels' documented limits                       */
+
+/* ---- options ---------------------------------------------------------- */
+#define TRG_MODEL_ISING 0
+
+#define TRG_FP64   0   /* every contraction in FP64 (MFMA f64)                                     */
+#define TRG_FP32   1   /* coarse-graining contractions (makeMG/makeMH) in FP32 MFMA; rest FP64     */
+#define TRG_BF16X3 2   /* coarse-graining contractions as 3-way split BF16 MFMA, FP32 accumulate   */
+
+#define TRG_SVD_SKETCH 0  /* bond swap by the randomized SVD of App. A (power_iters passes)         */
+#define TRG_SVD_EXACT  1  /* bond swap by the exact SVD of the QR-reduced core of App. A            */
+
+typedef struct trg_options {
+    int dim;            /* lattice dimension: 4 (2 and 3 accepted for atrg_step)                   */
+    int r;              /* overspanning parameter r of Sec. II A (triad bond R = min(r D, d1 d2))   */
+    int sketch_mult;    /* sketch width m = sketch_mult * D (App. A footnote: eta D)                */
+    int power_iters;    /* extra power passes of the randomized SVD (App. A loop count q = this+1) */
+    uint64_t seed;      /* Philox4x32-10 key of the Gaussian sketch                                */
+    uint32_t instance;  /* Philox counter word 2 (distinguishes independent solves)                */
+    int precision;      /* TRG_FP64 / TRG_FP32 / TRG_BF16X3                                        */
+    int bond_svd;       /* TRG_SVD_SKETCH / TRG_SVD_EXACT                                          */
+    int max_sweeps;     /* Jacobi sweep limit (0: default 60)                                       */
+    size_t workspace_cap; /* bytes of device workspace the state may hold (0: unlimited)           */
+    void *stream;       /* hipStream_t to enqueue on, or NULL for the null stream                  */
+    int device;         /* HIP device ordinal                                                      */
+} trg_options;
+
+/* Fills *opt with the defaults: dim 4, r 7, sketch_mult 2, power_iters 1,
+ * seed 0, instance 0, FP64, sketch, max_sweeps 60, no cap, NULL stream,
+ * device 0. */
+void trg_default_options(trg_options *opt);
+
+typedef struct trg_state trg_state;
+
+/* Creates a state (no tensors yet).  *out is NULL on failure. */
+int trg_create(const trg_options *opt, trg_state **out);
+
+/* Frees the state and its device memory.  NULL is accepted (no-op). */
+int trg_destroy(trg_state *s);
+
+/*
+ * tensor_init -- Ising initial tensor in CP form (Sec. III):
+ *   T[i_1..i_d; j_1..j_d] = sum_a exp(h s_a) prod_mu W[a,i_mu] W[a,j_mu],
+ *   W = [[sqrt cosh beta, sqrt sinh beta], [sqrt cosh beta, -sqrt sinh beta]],
+ * kept as the pair (Phi, Psi) with T = sum_g Phi[.., g] Psi[.., g].
+ * model must be TRG_MODEL_ISING, beta >= 0, D >= 2 (bond dimension cap).
+ * Resets the step count and the log-norm accumulator; may be called again.
+ */
+int tensor_init(trg_state *s, int model, double beta, double h, int D);
+
+/*
+ * atrg_step -- one ATRG coarse-graining step along `axis` (0..dim-1):
+ * exact re-split of T (Fig. 5f), bond swap (eq. of the bond swap, App. A),
+ * squeezers from the canonical Gamma^ATRG and makeG / makeH (Sec. II A).
+ * Halves the lattice along `axis`.  Asynchronous.
+ */
+int atrg_step(trg_state *s, int axis);
+
+/*
+ * triad_atrg_step -- one triad-ATRG step along `axis` (dim must be 4):
+ * re-split, bond swap, triad isometries from the truncated HOSVD of
+ * Gamma^ATRG (eq. HOSVD), triad tensors E..L, squeezers from Gamma^Triad
+ * with the Gram matrices O and P (Sec. II D), makeMG / makeMH (Sec. II B).
+ * Asynchronous.
+ */
+int triad_atrg_step(trg_state *s, int axis);
+
+/*
+ * log_z_per_site -- log Z / V of the torus the state represents (extent
+ * 2^(steps along mu) on axis mu): sum_k 2^-k log c_k + 2^-n log tTr T^(n)
+ * (eq. Z), with c_k the norm removed at the k-th re-split.  Synchronises;
+ * writes one double to *out (host).  TRG_E_NUMERICAL if the trace <= 0.
+ */
+int log_z_per_site(trg_state *s, double *out);
+
+/* ---- inspection (tests and benchmarks) --------------------------------- */
+
+/* Names accepted by trg_export (host copy of a device tensor). */
+#define TRG_T_PHI    0   /* Phi  [dims..., chi], natural axis order, FP64 */
+#define TRG_T_PSI    1   /* Psi  [dims..., chi]                           */
+#define TRG_T_SIGMA  2   /* bond-swap singular values of the last step    */
+
+/* Shape of the current state: dims[0..dim-1] leg dims, *chi the bond. */
+int trg_shape(trg_state *s, int *dims, int *chi, int *steps);
+
+/* Copies tensor `which` to host_dst (bytes must equal its size in bytes). */
+int trg_export(trg_state *s, int which, void *host_dst, size_t bytes);
+
+/* Byte size of tensor `which` (0 if not available). */
+size_t trg_export_size(trg_state *s, int which);
+
+/*
+ * Per-kernel timing of the last step: the library records HIP events
+ * around the coarse-graining GEMMs (makeMG / makeMH) when enabled.
+ * trg_set_timing(s, 1) enables; trg_kernel_time returns the summed
+ * milliseconds and the algorithmic flop count of those GEMMs since the
+ * last reset, and resets them.
+ */
+int trg_set_timing(trg_state *s, int enable);
+int trg_kernel_time(trg_state *s, double *ms, double *flops, int *launches);
+
+const char *trg_strerror(int code);
+const char *trg_last_error(trg_state *s);
+
+/* ---- kernel self-tests (host buffers in and out; tests only) ------------
+ * Each copies its host inputs to the device, runs one kernel of the path,
+ * and copies the result back.  Row-major storage throughout. */
+
+/* C[b] = A[b] op B[b] in FP64 MFMA: A (M x K, or K x M if ta), B (K x N, or
+ * N x K if tb), C (M x N), batch b with strides M*K, K*N, M*N.  precision
+ * selects FP64 / FP32 / BF16X3 arithmetic. */
+int trg_selftest_gemm(int precision, int ta, int tb, int M, int N, int K, int batch,
+                      const double *A, const double *B, double *C);
+
+/* Thin QR of A (m x n, m >= n, n <= 64) by the LDS Householder TSQR:
+ * Q (m x n), R (n x n) with diag(R) >= 0. */
+int trg_selftest_tsqr(int m, int n, const double *A, double *Q, double *R);
+
+/* One-sided Jacobi SVD of A (m x n, m >= n): U (m x n), s (n) descending,
+ * V (n x n).  Returns the number of sweeps in *sweeps. */
+int trg_selftest_svd(int m, int n, const double *A, double *U, double *s, double *V, int *sweeps);
+
+/* Gaussian sketch entries Omega[beta, j1, j2, j3, m] (layout as named) drawn
+ * exactly as the bond swap of step `step` draws them. */
+int trg_selftest_sketch(uint64_t seed, int step, uint32_t instance, int chi,
+                        int j1, int j2, int j3, int m, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRG_H */

@@ -1,0 +1,203 @@
+"""ctypes binding of libtrg.so (argument marshalling only).
+
+The names follow the C ABI of include/trg.h: ``Solver.tensor_init``,
+``Solver.atrg_step``, ``Solver.triad_atrg_step``, ``Solver.log_z_per_site``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtrg.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+SVD_SKETCH, SVD_EXACT = 0, 1
+MODEL_ISING = 0
+T_PHI, T_PSI, T_SIGMA = 0, 1, 2
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("r", ctypes.c_int),
+        ("sketch_mult", ctypes.c_int),
+        ("power_iters", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("instance", ctypes.c_uint32),
+        ("precision", ctypes.c_int),
+        ("bond_svd", ctypes.c_int),
+        ("max_sweeps", ctypes.c_int),
+        ("workspace_cap", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+        ("device", ctypes.c_int),
+    ]
+
+
+class TrgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("trg error %d: %s" % (code, msg))
+        self.code = code
+
+
+_LIB = None
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def load_library(path=None):
+    """Load libtrg.so (raises FileNotFoundError if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise FileNotFoundError("libtrg.so not built: run paper_2507_21909_amd/build.py (%s)" % path)
+    lib = ctypes.CDLL(path)
+    st = ctypes.c_void_p
+    lib.trg_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.trg_default_options.restype = None
+    lib.trg_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(st)]
+    lib.trg_destroy.argtypes = [st]
+    lib.tensor_init.argtypes = [st, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    lib.atrg_step.argtypes = [st, ctypes.c_int]
+    lib.triad_atrg_step.argtypes = [st, ctypes.c_int]
+    lib.log_z_per_site.argtypes = [st, _DP]
+    lib.trg_shape.argtypes = [st, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                              ctypes.POINTER(ctypes.c_int)]
+    lib.trg_export.argtypes = [st, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t]
+    lib.trg_export_size.argtypes = [st, ctypes.c_int]
+    lib.trg_export_size.restype = ctypes.c_size_t
+    lib.trg_set_timing.argtypes = [st, ctypes.c_int]
+    lib.trg_kernel_time.argtypes = [st, _DP, _DP, ctypes.POINTER(ctypes.c_int)]
+    lib.trg_strerror.argtypes = [ctypes.c_int]
+    lib.trg_strerror.restype = ctypes.c_char_p
+    lib.trg_last_error.argtypes = [st]
+    lib.trg_last_error.restype = ctypes.c_char_p
+    lib.trg_selftest_gemm.argtypes = [ctypes.c_int] * 7 + [_DP, _DP, _DP]
+    lib.trg_selftest_tsqr.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP]
+    lib.trg_selftest_svd.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP, _DP, ctypes.POINTER(ctypes.c_int)]
+    lib.trg_selftest_sketch.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32] + [ctypes.c_int] * 5 + [_DP]
+    for f in ("trg_create", "trg_destroy", "tensor_init", "atrg_step", "triad_atrg_step", "log_z_per_site",
+              "trg_shape", "trg_export", "trg_set_timing", "trg_kernel_time", "trg_selftest_gemm",
+              "trg_selftest_tsqr", "trg_selftest_svd", "trg_selftest_sketch"):
+        getattr(lib, f).restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_DP)
+
+
+def _check(rc, state=None):
+    if rc != 0:
+        lib = load_library()
+        msg = lib.trg_last_error(state).decode() if state is not None else lib.trg_last_error(None).decode()
+        raise TrgError(rc, "%s (%s)" % (lib.trg_strerror(rc).decode(), msg))
+
+
+class Solver:
+    """One ATRG / triad-ATRG solve on one GPU (a trg_state)."""
+
+    def __init__(self, dim=4, r=7, sketch_mult=2, power_iters=1, seed=0, instance=0, precision=FP64,
+                 bond_svd=SVD_SKETCH, max_sweeps=60, workspace_cap=0, stream=None, device=0):
+        lib = load_library()
+        o = Options()
+        lib.trg_default_options(ctypes.byref(o))
+        o.dim, o.r, o.sketch_mult, o.power_iters = dim, r, sketch_mult, power_iters
+        o.seed, o.instance, o.precision, o.bond_svd = seed, instance, precision, bond_svd
+        o.max_sweeps, o.workspace_cap, o.device = max_sweeps, workspace_cap, device
+        o.stream = stream
+        self._lib = lib
+        self._s = ctypes.c_void_p()
+        _check(lib.trg_create(ctypes.byref(o), ctypes.byref(self._s)))
+        self.dim = dim
+
+    def close(self):
+        if self._s:
+            self._lib.trg_destroy(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tensor_init(self, model, beta, h, D):
+        _check(self._lib.tensor_init(self._s, model, beta, h, D), self._s)
+
+    def atrg_step(self, axis):
+        _check(self._lib.atrg_step(self._s, axis), self._s)
+
+    def triad_atrg_step(self, axis):
+        _check(self._lib.triad_atrg_step(self._s, axis), self._s)
+
+    def log_z_per_site(self):
+        out = ctypes.c_double()
+        _check(self._lib.log_z_per_site(self._s, ctypes.byref(out)), self._s)
+        return out.value
+
+    def shape(self):
+        dims = (ctypes.c_int * self.dim)()
+        chi, steps = ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.trg_shape(self._s, dims, ctypes.byref(chi), ctypes.byref(steps)), self._s)
+        return tuple(dims), chi.value, steps.value
+
+    def export(self, which):
+        n = self._lib.trg_export_size(self._s, which)
+        out = np.empty(n // 8, dtype=np.float64)
+        _check(self._lib.trg_export(self._s, which, out.ctypes.data_as(ctypes.c_void_p), n), self._s)
+        if which in (T_PHI, T_PSI):
+            dims, chi, _ = self.shape()
+            out = out.reshape(tuple(dims) + (chi,))
+        return out
+
+    def set_timing(self, on=True):
+        _check(self._lib.trg_set_timing(self._s, 1 if on else 0), self._s)
+
+    def kernel_time(self):
+        ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        _check(self._lib.trg_kernel_time(self._s, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n)), self._s)
+        return ms.value, fl.value, n.value
+
+
+def selftest_gemm(a, b, ta=False, tb=False, precision=FP64):
+    """C[b] = op(A[b]) op(B[b]) on the GPU; a: (batch, M, K) or (batch, K, M) if ta."""
+    lib = load_library()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    batch = a.shape[0]
+    m, k = (a.shape[2], a.shape[1]) if ta else (a.shape[1], a.shape[2])
+    n = b.shape[1] if tb else b.shape[2]
+    c = np.empty((batch, m, n))
+    _check(lib.trg_selftest_gemm(precision, int(ta), int(tb), m, n, k, batch, _p(a), _p(b), _p(c)))
+    return c
+
+
+def selftest_tsqr(a):
+    lib = load_library()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    m, n = a.shape
+    q = np.empty((m, n))
+    r = np.empty((n, n))
+    _check(lib.trg_selftest_tsqr(m, n, _p(a), _p(q), _p(r)))
+    return q, r
+
+
+def selftest_svd(a):
+    lib = load_library()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    m, n = a.shape
+    u, s, v = np.empty((m, n)), np.empty(n), np.empty((n, n))
+    sw = ctypes.c_int()
+    _check(lib.trg_selftest_svd(m, n, _p(a), _p(u), _p(s), _p(v), ctypes.byref(sw)))
+    return u, s, v, sw.value
+
+
+def selftest_sketch(seed, step, instance, chi, jdims, m):
+    lib = load_library()
+    jd = list(jdims) + [1] * (3 - len(jdims))
+    out = np.empty((chi, jd[0], jd[1], jd[2], m))
+    _check(lib.trg_selftest_sketch(seed, step, instance, chi, jd[0], jd[1], jd[2], m, _p(out)))
+    return out.reshape([chi] + list(jdims) + [m])

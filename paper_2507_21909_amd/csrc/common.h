@@ -1,0 +1,98 @@
+// Shared declarations of the gfx950 kernels and the host engine.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace trg {
+
+// Error raised inside the library; converted to a TRG_E_* code at the ABI.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define TRG_HIP_CHECK(expr)                                                              \
+    do {                                                                                 \
+        hipError_t _e = (expr);                                                          \
+        if (_e != hipSuccess)                                                            \
+            throw ::trg::Error(-5, std::string(#expr) + ": " + hipGetErrorString(_e));   \
+    } while (0)
+
+#define TRG_REQUIRE(cond, code, msg)                                                     \
+    do {                                                                                 \
+        if (!(cond)) throw ::trg::Error((code), (msg));                                   \
+    } while (0)
+
+enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16X3 = 2 };
+
+// ---- GEMM: C[b] = alpha * sum_k A[b](r,k) B[b](k,n) + beta * C[b] -----------------
+// Element (r, k) of A[b] is at A + b*sAb + r*sAr + k*sAk (likewise B, C).
+struct GemmArgs {
+    int M, N, K, batch;
+    const double *A; long sAr, sAk, sAb;
+    const double *B; long sBk, sBn, sBb;
+    double *C; long sCr, sCn, sCb;
+    double alpha, beta;
+};
+void gemm(const GemmArgs &g, Prec prec, hipStream_t st);
+void gemm_f64(const GemmArgs &g, hipStream_t st);
+
+// ---- element-wise / layout kernels (kernels.hip) -----------------------------------
+// dst = src with axes permuted: dst dims = src dims[perm[i]].
+void permute(const double *src, double *dst, const std::vector<int> &dims,
+             const std::vector<int> &perm, hipStream_t st);
+// t[..., i_axis, ...] *= v[i_axis]^power (power 1 or 2 or -0.5) ; in place.
+void scale_axis(double *t, const std::vector<int> &dims, int axis, const double *v,
+                int mode, hipStream_t st);
+void fill(double *p, size_t n, double v, hipStream_t st);
+void copy(double *dst, const double *src, size_t n, hipStream_t st);
+
+// ---- small device helpers (kernels.hip) ---------------------------------------------
+// kept count of a descending vector (rule shared with every truncation)
+void kept_count(const double *vals, int n, int cap, double eps_rel, double tau_deg,
+                int *kept_dev, hipStream_t st);
+// zero columns j >= *kept of a row-major (rows x cols) matrix; also vals[j] if given
+void zero_tail_cols(double *a, long rows, int cols, long ld, const int *kept_dev,
+                    hipStream_t st);
+// sign convention: sg[j] = sign(sum_i w(i) Q[i,j]); row multi-index decoded from
+// `dims` (row-major over the GPU layout), each leg contributing idx * pw[leg].
+void sign_vector(const double *q, long rows, int cols, long ld, const std::vector<int> &dims,
+                 const std::vector<double> &pw, double *sg, hipStream_t st);
+// a[:, j] *= sg[j]
+void scale_cols(double *a, long rows, int cols, long ld, const double *sg, hipStream_t st);
+
+void philox_sketch(double *out, uint64_t seed, int step, uint32_t instance,
+                   const std::vector<int> &jdims, int chi, int m, int layout_jbm,
+                   hipStream_t st);
+
+// ---- factorizations -----------------------------------------------------------------
+// Thin QR of a (m x n, row-major, ld = n), n <= 64: q (m x n), r (n x n), diag r >= 0.
+// ws must hold tsqr_ws_doubles(m, n) doubles.
+size_t tsqr_ws_doubles(long m, int n);
+void tsqr(const double *a, long m, int n, double *q, double *r, double *ws, hipStream_t st);
+
+// One-sided Jacobi SVD of `count` matrices.  Each matrix is given column-major
+// (ut: n columns of m entries, column j at ut + j*m); on return the columns hold
+// U S (unsorted) and vt holds V column-major (n columns of n).  Returns sweeps.
+struct JacobiBatch {
+    int count, m, n;
+    double *ut;   // count * n * m
+    double *vt;   // count * n * n
+    long strideU, strideV;
+};
+// work: count * (n + 1) doubles (per-matrix scale, then column norms).
+int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *work, hipStream_t st);
+// After jacobi_svd: s (count x n) descending singular values, U columns normalized
+// and sorted into u_sorted (row-major m x n, may be null), V sorted into v_sorted
+// (row-major n x n).
+void jacobi_finish(const JacobiBatch &jb, double *s, double *u_sorted, double *v_sorted,
+                   double *work, hipStream_t st);
+
+inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace trg

@@ -1,0 +1,59 @@
+// Host engine of the RG step: device arena, tensor contraction over labelled
+// legs, and the state of one solve.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/trg.h"
+#include "common.h"
+
+namespace trg {
+
+// Bump allocator over device chunks; mark/release gives stack-like scopes.
+class Arena {
+  public:
+    explicit Arena(size_t cap = 0) : cap_(cap) {}
+    ~Arena();
+    void *alloc(size_t bytes);
+    double *dalloc(size_t n) { return static_cast<double *>(alloc(n * sizeof(double))); }
+    struct Mark { size_t chunk, used; };
+    Mark mark() const;
+    void release(const Mark &m);
+    void reset() { release(Mark{0, 0}); }
+    size_t held() const { return total_; }
+    void set_cap(size_t c) { cap_ = c; }
+
+  private:
+    struct Chunk { char *base; size_t cap, used; };
+    std::vector<Chunk> chunks_;
+    size_t cur_ = 0, total_ = 0, cap_ = 0;
+};
+
+// Device tensor: row-major, leftmost leg slowest.
+struct DT {
+    double *p = nullptr;
+    std::vector<int> d;
+    long n() const {
+        long x = 1;
+        for (int v : d) x *= v;
+        return x;
+    }
+};
+
+struct Ctx {
+    hipStream_t st;
+    Arena *ar;
+    Prec prec;
+    // optional timing of selected GEMMs
+    bool timing = false;
+    double ms = 0.0, flops = 0.0;
+    int launches = 0;
+};
+
+DT talloc(Ctx &c, std::vector<int> dims);
+DT permuted(Ctx &c, const DT &a, const std::string &la, const std::string &lt);
+// out[lo] = alpha * sum a[la] b[lb] ; labels are single characters.
+DT contract(Ctx &c, const DT &a, const std::string &la, const DT &b, const std::string &lb,
+            const std::string &lo, Prec prec = P_FP64, double alpha = 1.0);
+
+}  // namespace trg

@@ -1,0 +1,122 @@
+// Batched GEMM over arbitrarily strided operands on the gfx950 matrix cores.
+//
+// Every contraction of the RG step (Sec. II A-B) is evaluated as a GEMM over
+// reshaped tensor legs; the strides let one kernel read operands in the
+// layout the previous step left them in (row- or column-major, batched).
+//
+// FP64 path: v_mfma_f64_16x16x4_f64.  A 256-thread workgroup owns a 64x64
+// tile of C; its four wavefronts own 32x32 quadrants (2x2 MFMA tiles).  K is
+// staged through LDS in slabs of 16, K-major, and the next slab is fetched
+// into registers while the current one is multiplied.
+#include "common.h"
+
+namespace trg {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+namespace {
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256, LP = 4;  // LP: LDS row padding
+
+__global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
+    const int bz = blockIdx.z;
+    const double *A = g.A + (long)bz * g.sAb;
+    const double *B = g.B + (long)bz * g.sBb;
+    double *C = g.C + (long)bz * g.sCb;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+
+    __shared__ double As[BK][BM + LP];
+    __shared__ double Bs[BK][BN + LP];
+
+    // loader mapping (4 elements per thread per operand)
+    const bool a_kfast = (g.sAk == 1) || (g.sAr != 1);
+    const bool b_nfast = (g.sBn == 1) || (g.sBk != 1);
+    int ar, ak, br, bk;  // base row/k of this thread's 4 A elements, k/col of B
+    if (a_kfast) { ar = t >> 2; ak = (t & 3) * 4; } else { ak = t >> 4; ar = (t & 15) * 4; }
+    if (b_nfast) { bk = t >> 4; br = (t & 15) * 4; } else { br = t >> 2; bk = (t & 3) * 4; }
+
+    double ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int r = m0 + (a_kfast ? ar : ar + i), k = k0 + (a_kfast ? ak + i : ak);
+            ra[i] = (r < g.M && k < g.K) ? A[(long)r * g.sAr + (long)k * g.sAk] : 0.0;
+            int c = n0 + (b_nfast ? br + i : br), kb = k0 + (b_nfast ? bk : bk + i);
+            rb[i] = (c < g.N && kb < g.K) ? B[(long)kb * g.sBk + (long)c * g.sBn] : 0.0;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (a_kfast) As[ak + i][ar] = ra[i]; else As[ak][ar + i] = ra[i];
+            if (b_nfast) Bs[bk][br + i] = rb[i]; else Bs[bk + i][br] = rb[i];
+        }
+    };
+
+    d4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int nk = (g.K + BK - 1) / BK;
+    load(0);
+    store();
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            double af[2], bf[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) af[i] = As[kr][wr * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bf[j] = Bs[kr][wc * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            store();
+            __syncthreads();
+        }
+    }
+    // epilogue: lane holds D[4*(lane/16)+i][lane%16] of each 16x16 tile
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int r = m0 + wr * 32 + i * 16 + 4 * (lane >> 4) + e;
+                int c = n0 + wc * 32 + j * 16 + (lane & 15);
+                if (r < g.M && c < g.N) {
+                    double *p = C + (long)r * g.sCr + (long)c * g.sCn;
+                    double v = g.alpha * acc[i][j][e];
+                    if (g.beta != 0.0) v += g.beta * *p;
+                    *p = v;
+                }
+            }
+}
+}  // namespace
+
+void gemm_f64(const GemmArgs &g, hipStream_t st) {
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+    for (int b0 = 0; b0 < g.batch; b0 += 65535) {
+        GemmArgs h = g;
+        h.batch = std::min(65535, g.batch - b0);
+        h.A += (long)b0 * g.sAb;
+        h.B += (long)b0 * g.sBb;
+        h.C += (long)b0 * g.sCb;
+        dim3 grid(cdiv(h.N, BN), cdiv(h.M, BM), h.batch);
+        hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, st, h);
+    }
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace trg

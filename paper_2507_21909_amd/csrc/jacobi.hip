@@ -1,0 +1,213 @@
+// One-sided (Hestenes) Jacobi SVD for the truncated SVDs and eigen-
+// decompositions of the RG step: the re-split SVD (Fig. 5f), the SVD of the
+// projected bond-swap matrix (App. A), the exact bond-swap SVD, the triad
+// HOSVD Grams (eq. HOSVD) and the squeezer square roots and SVDs (Sec. II A).
+// For a symmetric positive semi-definite Gram K, K V = U S gives its
+// eigenvectors V and eigenvalues S.
+//
+// Matrices are held column by column (column j contiguous, m entries).  A
+// round of the circle-method tournament rotates n/2 disjoint column pairs; one
+// wavefront owns one pair: three dot products over the m rows (wave
+// reductions), the rotation of Rutishauser's formulas, and the update of the
+// two columns of U and of V.  Large n: one launch per round, all matrices of a
+// batch together.  Small n: one workgroup per matrix loops over every round
+// and sweep in a single launch.
+#include <cmath>
+
+#include "common.h"
+
+namespace trg {
+
+namespace {
+constexpr int NT = 256;
+
+__device__ inline int player_at(int mm, int i, int r) { return i == 0 ? 0 : 1 + ((i - 1 + r) % (mm - 1)); }
+
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// rotate pair k of round r of matrix (u, v); returns true if rotated
+__device__ bool rotate_pair(double *u, double *v, int m, int n, int mm, int r, int k, double tol) {
+    const int lane = threadIdx.x & 63;
+    int a = player_at(mm, k, r), b = player_at(mm, mm - 1 - k, r);
+    if (a >= n || b >= n) return false;
+    int p = a < b ? a : b, q = a < b ? b : a;
+    double *up = u + (long)p * m, *uq = u + (long)q * m;
+    double al = 0.0, be = 0.0, ga = 0.0;
+    for (int i = lane; i < m; i += 64) {
+        double x = up[i], y = uq[i];
+        al += x * x;
+        be += y * y;
+        ga += x * y;
+    }
+    al = wave_sum(al);
+    be = wave_sum(be);
+    ga = wave_sum(ga);
+    if (al < 1e-280 || be < 1e-280 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) return false;
+    double zeta = (be - al) / (2.0 * ga);
+    double t = zeta == 0.0 ? 1.0 : copysign(1.0, zeta) / (fabs(zeta) + hypot(zeta, 1.0));
+    double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+    for (int i = lane; i < m; i += 64) {
+        double x = up[i], y = uq[i];
+        up[i] = c * x - s * y;
+        uq[i] = s * x + c * y;
+    }
+    double *vp = v + (long)p * n, *vq = v + (long)q * n;
+    for (int i = lane; i < n; i += 64) {
+        double x = vp[i], y = vq[i];
+        vp[i] = c * x - s * y;
+        vq[i] = s * x + c * y;
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(NT) void round_kernel(JacobiBatch jb, int r, double tol, int *flags) {
+    const int mat = blockIdx.y;
+    const int k = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+    const int mm = jb.n + (jb.n & 1);
+    if (k >= mm / 2) return;
+    double *u = jb.ut + (long)mat * jb.strideU;
+    double *v = jb.vt + (long)mat * jb.strideV;
+    if (rotate_pair(u, v, jb.m, jb.n, mm, r, k, tol) && (threadIdx.x & 63) == 0) flags[mat] = 1;
+}
+
+__global__ __launch_bounds__(NT) void full_kernel(JacobiBatch jb, int max_sweeps, double tol, int *flags) {
+    const int mat = blockIdx.x;
+    double *u = jb.ut + (long)mat * jb.strideU;
+    double *v = jb.vt + (long)mat * jb.strideV;
+    const int mm = jb.n + (jb.n & 1);
+    const int w = threadIdx.x >> 6;
+    __shared__ int rot;
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
+        if (threadIdx.x == 0) rot = 0;
+        __syncthreads();
+        for (int r = 0; r < mm - 1; ++r) {
+            for (int k = w; k < mm / 2; k += NT / 64)
+                if (rotate_pair(u, v, jb.m, jb.n, mm, r, k, tol) && (threadIdx.x & 63) == 0) rot = 1;
+            __syncthreads();
+        }
+        if (rot == 0) break;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) flags[mat] = sweep < max_sweeps ? sweep : -1;
+}
+
+__global__ void init_v_kernel(JacobiBatch jb) {
+    long tot = (long)jb.count * jb.n * jb.n;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
+        long mat = i / ((long)jb.n * jb.n), rem = i - mat * jb.n * jb.n;
+        int col = (int)(rem / jb.n), row = (int)(rem % jb.n);
+        jb.vt[mat * jb.strideV + (long)col * jb.n + row] = row == col ? 1.0 : 0.0;
+    }
+}
+
+// per-matrix max |u| -> scale[mat]; u /= scale
+__global__ void scale_kernel(JacobiBatch jb, double *scale) {
+    const int mat = blockIdx.x;
+    double *u = jb.ut + (long)mat * jb.strideU;
+    long tot = (long)jb.m * jb.n;
+    double mx = 0.0;
+    for (long i = threadIdx.x; i < tot; i += blockDim.x) mx = fmax(mx, fabs(u[i]));
+    __shared__ double red[NT];
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    double f = red[0] > 0.0 ? red[0] : 1.0;
+    if (threadIdx.x == 0) scale[mat] = f;
+    for (long i = threadIdx.x; i < tot; i += blockDim.x) u[i] /= f;
+}
+
+// norms of the columns (one wave per column)
+__global__ void norms_kernel(JacobiBatch jb, const double *scale, double *nrm) {
+    const int mat = blockIdx.y;
+    const int j = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+    if (j >= jb.n) return;
+    const double *u = jb.ut + (long)mat * jb.strideU + (long)j * jb.m;
+    double s = 0.0;
+    for (int i = threadIdx.x & 63; i < jb.m; i += 64) s += u[i] * u[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) nrm[(long)mat * jb.n + j] = sqrt(s);
+}
+
+// rank of every column in descending norm order (ties by index), then gather
+__global__ void sort_gather_kernel(JacobiBatch jb, const double *scale, const double *nrm, double *s,
+                                   double *us, double *vs) {
+    const int mat = blockIdx.y;
+    const int j = blockIdx.x;
+    const double *nm = nrm + (long)mat * jb.n;
+    const double sj = nm[j];
+    __shared__ int rank_sh;
+    if (threadIdx.x == 0) rank_sh = 0;
+    __syncthreads();
+    int cnt = 0;
+    for (int k = threadIdx.x; k < jb.n; k += blockDim.x) {
+        double sk = nm[k];
+        cnt += (sk > sj || (sk == sj && k < j)) ? 1 : 0;
+    }
+    atomicAdd(&rank_sh, cnt);
+    __syncthreads();
+    const int rk = rank_sh;
+    if (threadIdx.x == 0) s[(long)mat * jb.n + rk] = sj * scale[mat];
+    const double *u = jb.ut + (long)mat * jb.strideU + (long)j * jb.m;
+    const double *v = jb.vt + (long)mat * jb.strideV + (long)j * jb.n;
+    double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+    if (us) {
+        double *uo = us + (long)mat * jb.m * jb.n;
+        for (int i = threadIdx.x; i < jb.m; i += blockDim.x) uo[(long)i * jb.n + rk] = u[i] * inv;
+    }
+    double *vo = vs + (long)mat * jb.n * jb.n;
+    for (int i = threadIdx.x; i < jb.n; i += blockDim.x) vo[(long)i * jb.n + rk] = v[i];
+}
+}  // namespace
+
+int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *work, hipStream_t st) {
+    if (jb.count == 0 || jb.n == 0) return 0;
+    const double tol = sqrt((double)jb.m) * 2.220446049250313e-16;
+    hipLaunchKernelGGL(scale_kernel, dim3(jb.count), dim3(NT), 0, st, jb, work);
+    hipLaunchKernelGGL(init_v_kernel, dim3(cdiv((size_t)jb.count * jb.n * jb.n, 256)), dim3(256), 0, st, jb);
+    TRG_HIP_CHECK(hipGetLastError());
+    const int mm = jb.n + (jb.n & 1);
+    std::vector<int> fl(jb.count);
+    if (jb.n <= 96) {
+        hipLaunchKernelGGL(full_kernel, dim3(jb.count), dim3(NT), 0, st, jb, max_sweeps, tol, flags_dev);
+        TRG_HIP_CHECK(hipGetLastError());
+        TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), flags_dev, sizeof(int) * jb.count, hipMemcpyDeviceToHost, st));
+        TRG_HIP_CHECK(hipStreamSynchronize(st));
+        int worst = 0;
+        for (int f : fl) {
+            TRG_REQUIRE(f >= 0, -4, "Jacobi SVD did not converge");
+            worst = std::max(worst, f);
+        }
+        return worst;
+    }
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        TRG_HIP_CHECK(hipMemsetAsync(flags_dev, 0, sizeof(int) * jb.count, st));
+        dim3 grid(cdiv(mm / 2, NT / 64), jb.count);
+        for (int r = 0; r < mm - 1; ++r) hipLaunchKernelGGL(round_kernel, grid, dim3(NT), 0, st, jb, r, tol, flags_dev);
+        TRG_HIP_CHECK(hipGetLastError());
+        TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), flags_dev, sizeof(int) * jb.count, hipMemcpyDeviceToHost, st));
+        TRG_HIP_CHECK(hipStreamSynchronize(st));
+        bool any = false;
+        for (int f : fl) any |= f != 0;
+        if (!any) return sweep;
+    }
+    throw Error(-4, "Jacobi SVD did not converge");
+}
+
+void jacobi_finish(const JacobiBatch &jb, double *s, double *u_sorted, double *v_sorted, double *work,
+                   hipStream_t st) {
+    // work: count (scale) + count*n (norms)
+    double *scale = work, *nrm = work + jb.count;
+    hipLaunchKernelGGL(norms_kernel, dim3(cdiv(jb.n, NT / 64), jb.count), dim3(NT), 0, st, jb, scale, nrm);
+    hipLaunchKernelGGL(sort_gather_kernel, dim3(jb.n, jb.count), dim3(NT), 0, st, jb, scale, nrm, s, u_sorted,
+                       v_sorted);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace trg

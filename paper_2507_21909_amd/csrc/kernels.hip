@@ -1,0 +1,310 @@
+// Layout, element-wise and bookkeeping kernels of the RG step.
+#include <cmath>
+
+#include "common.h"
+
+namespace trg {
+
+namespace {
+constexpr int MAXD = 8;
+struct PermArgs {
+    int nd;
+    long dd[MAXD];   // dst dims
+    long ss[MAXD];   // src stride of the axis that becomes dst axis i
+    long total;
+};
+
+__global__ void permute_kernel(const double *__restrict__ src, double *__restrict__ dst, PermArgs a) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < a.total; i += (long)gridDim.x * blockDim.x) {
+        long rem = i, off = 0;
+        for (int d = a.nd - 1; d >= 0; --d) {
+            long q = rem / a.dd[d];
+            off += (rem - q * a.dd[d]) * a.ss[d];
+            rem = q;
+        }
+        dst[i] = src[off];
+    }
+}
+
+// tiled 2-D transpose for the common case "swap two contiguous groups":
+// dst[b][c][r] = src[b][r][c]
+__global__ void transpose_kernel(const double *__restrict__ src, double *__restrict__ dst, long R, long Cc) {
+    __shared__ double tile[32][33];
+    long b = blockIdx.z;
+    long r0 = blockIdx.y * 32L, c0 = blockIdx.x * 32L;
+    const double *s = src + b * R * Cc;
+    double *d = dst + b * R * Cc;
+    int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        long r = r0 + k, c = c0 + tx;
+        tile[k][tx] = (r < R && c < Cc) ? s[r * Cc + c] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        long c = c0 + k, r = r0 + tx;
+        if (r < R && c < Cc) d[c * R + r] = tile[tx][k];
+    }
+}
+
+__global__ void scale_axis_kernel(double *t, long total, long inner, long dim, const double *v, int mode) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        long ax = (i / inner) % dim;
+        double x = v[ax];
+        double f = mode == 1 ? x : mode == 2 ? x * x : (x > 0.0 ? 1.0 / sqrt(x) : 0.0);
+        t[i] *= f;
+    }
+}
+
+__global__ void fill_kernel(double *p, long n, double v) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void copy_kernel(double *d, const double *s, long n) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
+}
+
+__global__ void kept_kernel(const double *v, int n, int cap, double eps, double tau, int *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int k = 0;
+    double top = n > 0 ? v[0] : 0.0;
+    if (n > 0 && top > 0.0) {
+        int nz = 0;
+        for (int i = 0; i < n; ++i) nz += v[i] > eps * top ? 1 : 0;
+        k = cap < nz ? cap : nz;
+        if (k < nz)
+            while (k > 0 && (v[k - 1] - v[k]) <= tau * top) --k;
+    }
+    *out = k;
+}
+
+__global__ void zero_tail_kernel(double *a, long rows, int cols, long ld, const int *kept) {
+    int k = *kept;
+    long n = rows * (long)cols;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        long r = i / cols;
+        int c = (int)(i - r * cols);
+        if (c >= k) a[r * ld + c] = 0.0;
+    }
+}
+
+struct SignArgs {
+    int nd;
+    long dd[MAXD];
+    double pw[MAXD];
+};
+
+// one workgroup per column; w(i) = 0.5 + frac(g (1 + sum_l idx_l pw_l))
+__global__ void sign_kernel(const double *q, long rows, int cols, long ld, SignArgs a, double *sg) {
+    const double golden = 0.6180339887498949;
+    int j = blockIdx.x;
+    double acc = 0.0;
+    for (long r = threadIdx.x; r < rows; r += blockDim.x) {
+        long rem = r;
+        double code = 0.0;
+        for (int d = a.nd - 1; d >= 0; --d) {
+            long qd = rem / a.dd[d];
+            code += (double)(rem - qd * a.dd[d]) * a.pw[d];
+            rem = qd;
+        }
+        double x = golden * (1.0 + code);
+        double wgt = 0.5 + (x - floor(x));
+        acc += wgt * q[r * ld + j];
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sg[j] = red[0] < 0.0 ? -1.0 : 1.0;
+}
+
+__global__ void scale_cols_kernel(double *a, long rows, int cols, long ld, const double *sg) {
+    long n = rows * (long)cols;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        long r = i / cols;
+        int c = (int)(i - r * cols);
+        a[r * ld + c] *= sg[c];
+    }
+}
+
+// Philox4x32-10 (Salmon et al., SC'11)
+__device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        uint64_t p0 = (uint64_t)M0 * c[0], p1 = (uint64_t)M1 * c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+struct SketchArgs {
+    uint32_t k0, k1, instance, step;
+    int j1, j2, j3, chi, m, layout_jbm;
+    long total;
+};
+
+// Omega entry for multi-index (beta, j1, j2, j3, m): standard normal from the
+// first two Philox words (Box-Muller, cosine branch).
+__global__ void sketch_kernel(double *out, SketchArgs a) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < a.total; i += (long)gridDim.x * blockDim.x) {
+        long rem = i;
+        int mm = (int)(rem % a.m); rem /= a.m;
+        int b, x1, x2, x3;
+        if (a.layout_jbm) {   // [j1, j2, j3, beta, m]
+            b = (int)(rem % a.chi); rem /= a.chi;
+            x3 = (int)(rem % a.j3); rem /= a.j3;
+            x2 = (int)(rem % a.j2); rem /= a.j2;
+            x1 = (int)rem;
+        } else {              // [beta, j1, j2, j3, m]
+            x3 = (int)(rem % a.j3); rem /= a.j3;
+            x2 = (int)(rem % a.j2); rem /= a.j2;
+            x1 = (int)(rem % a.j1); rem /= a.j1;
+            b = (int)rem;
+        }
+        uint32_t c[4] = {(uint32_t)x1 | ((uint32_t)x2 << 8) | ((uint32_t)x3 << 16) | ((uint32_t)b << 24),
+                         (uint32_t)mm | ((a.step & 0xFFFFu) << 16), a.instance, 0x4F4D4547u};
+        philox(c, a.k0, a.k1);
+        double u1 = ((double)c[0] + 0.5) * 0x1p-32;
+        double u2 = ((double)c[1] + 0.5) * 0x1p-32;
+        out[i] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+    }
+}
+
+inline unsigned grid_for(long n) { return (unsigned)std::min<long>((n + 255) / 256, 65536L); }
+}  // namespace
+
+void permute(const double *src, double *dst, const std::vector<int> &dims, const std::vector<int> &perm,
+             hipStream_t st) {
+    int nd = (int)dims.size();
+    TRG_REQUIRE(nd <= MAXD && (int)perm.size() == nd, -1, "permute: bad rank");
+    long total = 1;
+    for (int d : dims) total *= d;
+    if (total == 0) return;
+    // drop trivial permutations
+    bool ident = true;
+    for (int i = 0; i < nd; ++i) ident &= perm[i] == i;
+    if (ident) {
+        if (src != dst) copy(dst, src, (size_t)total, st);
+        return;
+    }
+    std::vector<long> sstr(nd);
+    long s = 1;
+    for (int d = nd - 1; d >= 0; --d) { sstr[d] = s; s *= dims[d]; }
+    // fast path: dst = [P, C, R] from src = [P, R, C] (two contiguous groups swapped)
+    for (int split_a = 0; split_a < nd; ++split_a) {
+        // prefix [0, split_a) fixed
+        bool pre = true;
+        for (int i = 0; i < split_a; ++i) pre &= perm[i] == i;
+        if (!pre) break;
+        for (int split_b = split_a + 1; split_b < nd; ++split_b) {
+            // src groups: R = [split_a, split_b), C = [split_b, nd); dst = prefix, C, R
+            bool ok = true;
+            int p = split_a;
+            for (int i = split_b; i < nd; ++i) ok &= perm[p++] == i;
+            for (int i = split_a; i < split_b; ++i) ok &= perm[p++] == i;
+            if (!ok) continue;
+            long P = 1, R = 1, Cc = 1;
+            for (int i = 0; i < split_a; ++i) P *= dims[i];
+            for (int i = split_a; i < split_b; ++i) R *= dims[i];
+            for (int i = split_b; i < nd; ++i) Cc *= dims[i];
+            if (P <= 65535) {
+                dim3 grid(cdiv(Cc, 32), cdiv(R, 32), (unsigned)P);
+                if (grid.y <= 65535) {
+                    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, st, src, dst, R, Cc);
+                    TRG_HIP_CHECK(hipGetLastError());
+                    return;
+                }
+            }
+        }
+    }
+    PermArgs a{};
+    a.nd = nd;
+    a.total = total;
+    for (int i = 0; i < nd; ++i) { a.dd[i] = dims[perm[i]]; a.ss[i] = sstr[perm[i]]; }
+    hipLaunchKernelGGL(permute_kernel, dim3(grid_for(total)), dim3(256), 0, st, src, dst, a);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
+void scale_axis(double *t, const std::vector<int> &dims, int axis, const double *v, int mode, hipStream_t st) {
+    long total = 1, inner = 1;
+    for (size_t d = 0; d < dims.size(); ++d) {
+        total *= dims[d];
+        if ((int)d > axis) inner *= dims[d];
+    }
+    if (total == 0) return;
+    hipLaunchKernelGGL(scale_axis_kernel, dim3(grid_for(total)), dim3(256), 0, st, t, total, inner,
+                       (long)dims[axis], v, mode);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
+void fill(double *p, size_t n, double v, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for((long)n)), dim3(256), 0, st, p, (long)n, v);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
+void copy(double *dst, const double *src, size_t n, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(copy_kernel, dim3(grid_for((long)n)), dim3(256), 0, st, dst, src, (long)n);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
+void kept_count(const double *vals, int n, int cap, double eps_rel, double tau_deg, int *kept_dev, hipStream_t st) {
+    hipLaunchKernelGGL(kept_kernel, dim3(1), dim3(64), 0, st, vals, n, cap, eps_rel, tau_deg, kept_dev);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
+void zero_tail_cols(double *a, long rows, int cols, long ld, const int *kept_dev, hipStream_t st) {
+    long n = rows * cols;
+    if (!n) return;
+    hipLaunchKernelGGL(zero_tail_kernel, dim3(grid_for(n)), dim3(256), 0, st, a, rows, cols, ld, kept_dev);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
+void sign_vector(const double *q, long rows, int cols, long ld, const std::vector<int> &dims,
+                 const std::vector<double> &pw, double *sg, hipStream_t st) {
+    SignArgs a{};
+    a.nd = (int)dims.size();
+    TRG_REQUIRE(a.nd <= MAXD && pw.size() == dims.size(), -1, "sign_vector: bad dims");
+    long prod = 1;
+    for (int i = 0; i < a.nd; ++i) { a.dd[i] = dims[i]; a.pw[i] = pw[i]; prod *= dims[i]; }
+    TRG_REQUIRE(prod == rows, -1, "sign_vector: dims do not match rows");
+    if (cols == 0) return;
+    hipLaunchKernelGGL(sign_kernel, dim3(cols), dim3(256), 0, st, q, rows, cols, ld, a, sg);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
+void scale_cols(double *a, long rows, int cols, long ld, const double *sg, hipStream_t st) {
+    long n = rows * cols;
+    if (!n) return;
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(grid_for(n)), dim3(256), 0, st, a, rows, cols, ld, sg);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
+void philox_sketch(double *out, uint64_t seed, int step, uint32_t instance, const std::vector<int> &jdims,
+                   int chi, int m, int layout_jbm, hipStream_t st) {
+    SketchArgs a{};
+    a.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    a.k1 = (uint32_t)(seed >> 32);
+    a.instance = instance;
+    a.step = (uint32_t)step;
+    a.j1 = jdims.size() > 0 ? jdims[0] : 1;
+    a.j2 = jdims.size() > 1 ? jdims[1] : 1;
+    a.j3 = jdims.size() > 2 ? jdims[2] : 1;
+    TRG_REQUIRE(a.j1 <= 256 && a.j2 <= 256 && a.j3 <= 256 && chi <= 256 && m <= 65536 && step <= 0xFFFF, -6,
+                "sketch: leg dims must be < 256 and m < 65536");
+    a.chi = chi;
+    a.m = m;
+    a.layout_jbm = layout_jbm;
+    a.total = (long)a.j1 * a.j2 * a.j3 * chi * m;
+    if (!a.total) return;
+    hipLaunchKernelGGL(sketch_kernel, dim3(grid_for(a.total)), dim3(256), 0, st, out, a);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace trg

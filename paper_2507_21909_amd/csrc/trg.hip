@@ -1,0 +1,1018 @@
+// The RG step of ATRG and triad-ATRG on one GPU, behind the C ABI of trg.h.
+//
+// Step along axis a, transverse axes (t1, t2, t3) = (a+1, a+2, a+3) mod 4:
+//  1. re-split T = Phi Psi^T exactly (Fig. 5f): TSQR of Phi and Psi, Jacobi SVD
+//     of R_Phi R_Psi^T, norm c_k into the log-norm accumulator;
+//  2. bond swap (App. A): randomized SVD applying M = sum_x B C directly to the
+//     sketch (no QR of B and C), or the exact SVD of the QR-reduced core;
+//  3a. ATRG (Sec. II A): squeezers from canonical Gamma^ATRG, makeG / makeH;
+//  3b. triad-ATRG (Sec. II B): triad isometries (eq. HOSVD), E..L, Gram
+//     matrices O and P (Sec. II D), squeezers from Gamma^Triad, makeMG / makeMH.
+// Every truncation keeps at most its cap, drops values at or below the
+// relative threshold and never cuts a multiplet (kept_count); kept vectors
+// get the sign convention of the weight w(multi-index).
+#include <cmath>
+#include <cstring>
+
+#include "engine.h"
+
+struct trg_state {
+    trg_options opt;
+    hipStream_t st = nullptr;
+    trg::Arena ar;
+    bool init = false;
+    int D = 0, k = 0, chi = 0;
+    double beta = 0.0, h = 0.0;
+    std::vector<int> dims;
+    double *phi = nullptr, *psi = nullptr;   // persistent state
+    size_t cap_state = 0;
+    double *dscal = nullptr;   // [0] logacc, [1] trace, [2..] scratch
+    int *dint = nullptr;       // [0] numerical status, [1..] flags / counts
+    std::vector<double> sigma_last;
+    std::string err;
+    bool timing = false;
+    double t_ms = 0.0, t_flops = 0.0;
+    int t_launch = 0;
+};
+
+namespace trg {
+namespace {
+
+constexpr double EPS_S = 1e-14, EPS_LAM = 1e-14, EPS_SQ = 1e-14, TAU_DEG = 1e-12;
+
+// ---------------------------------------------------------------- small kernels
+__global__ void resplit_norm_kernel(double *s, int n, int k, double *logacc, double eps, int *status) {
+    if (threadIdx.x || blockIdx.x) return;
+    double c = s[0];
+    if (!(c > 0.0) || !isfinite(c)) {
+        *status = 1;
+        c = 1.0;
+    }
+    *logacc += ldexp(log(c), -k);
+    for (int i = 0; i < n; ++i) {
+        double v = s[i] / c;
+        s[i] = v > eps ? v : 0.0;
+    }
+}
+
+__global__ void mask_sign_kernel(double *sg, const double *s, int n) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n && !(s[j] > 0.0)) sg[j] = 0.0;
+}
+
+// out[j] = sqrt(lam[j]) if lam[j] > eps * lam[0] else 0
+__global__ void sqrt_clamp_kernel(const double *lam, double *out, int n, double eps) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double top = lam[0] > 0.0 ? lam[0] : 0.0;
+    double v = lam[j];
+    out[j] = v > eps * top ? sqrt(v) : 0.0;
+}
+
+// out[j] = j < kept ? S[j]^-1/2 : 0
+__global__ void isqrt_kept_kernel(const double *s, double *out, int n, const int *kept) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    out[j] = j < *kept ? 1.0 / sqrt(s[j]) : 0.0;
+}
+
+__global__ void zero_tail_vec_kernel(double *v, int n, const int *kept) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n && j >= *kept) v[j] = 0.0;
+}
+
+__global__ void square_kernel(const double *v, double *o, int n) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) o[j] = v[j] * v[j];
+}
+
+__global__ void eye_kernel(double *a, int n) {
+    long tot = (long)n * n;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x)
+        a[i] = (i / n == i % n) ? 1.0 : 0.0;
+}
+
+// partial dot products of two vectors, then a final single-block sum
+__global__ void dot_partial_kernel(const double *a, const double *b, long n, double *part) {
+    double acc = 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        acc += a[i] * b[i];
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sum_kernel(const double *part, int n, double *out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+inline unsigned g1(long n) { return (unsigned)std::max(1L, std::min((n + 255) / 256, 65536L)); }
+
+// ---------------------------------------------------------------- helpers
+struct Step {
+    trg_state *S;
+    Ctx c;
+    int *kept;   // next free device int for a kept count
+    double *scr; // device scalar scratch
+    Step(trg_state *s) : S(s) {
+        c.st = s->st;
+        c.ar = &s->ar;
+        c.prec = P_FP64;
+        kept = s->dint + 8;
+    }
+    int *new_kept() { return kept++; }
+};
+
+std::vector<double> pow131(int nd) {
+    std::vector<double> p(nd);
+    double m = 1.0;
+    for (int i = 0; i < nd; ++i) { p[i] = m; m *= 131.0; }
+    return p;
+}
+
+// dst (rows x k) = first k columns of src (rows x cols), both row-major
+void col_slice(Ctx &c, const double *src, long rows, long cols, int k, double *dst) {
+    TRG_HIP_CHECK(hipMemcpy2DAsync(dst, sizeof(double) * k, src, sizeof(double) * cols, sizeof(double) * k, rows,
+                                   hipMemcpyDeviceToDevice, c.st));
+}
+
+// SVD of `count` matrices given column-major (a + i*m*n holds n columns of m):
+// s (count x n) descending, u (count x m x n) and v (count x n x n) row-major, sorted.
+void svd_colmajor(Step &T, const double *a, int count, int m, int n, double *s, double *u, double *v) {
+    Ctx &c = T.c;
+    double *ut = c.ar->dalloc((size_t)count * m * n);
+    copy(ut, a, (size_t)count * m * n, c.st);
+    double *vt = c.ar->dalloc((size_t)count * n * n);
+    double *work = c.ar->dalloc((size_t)count * (n + 1));
+    JacobiBatch jb{count, m, n, ut, vt, (long)m * n, (long)n * n};
+    int ms = T.S->opt.max_sweeps > 0 ? T.S->opt.max_sweeps : 60;
+    jacobi_svd(jb, ms, T.S->dint + 1, work, c.st);
+    jacobi_finish(jb, s, u, v, work, c.st);
+}
+
+// SVD of a row-major matrix a (m x n, m >= n)
+void svd_rowmajor(Step &T, const DT &a, double *s, double *u, double *v) {
+    int m = a.d[0], n = a.d[1];
+    DT at = permuted(T.c, a, "ij", "ji");   // column-major copy
+    svd_colmajor(T, at.p, 1, m, n, s, u, v);
+}
+
+// eigen-decomposition of symmetric PSD matrices (count x n x n): lam desc, vecs row-major
+void eig_psd(Step &T, const double *k, int count, int n, double *lam, double *vec) {
+    svd_colmajor(T, k, count, n, n, lam, nullptr, vec);
+}
+
+// ---------------------------------------------------------------- re-split
+struct Split {
+    DT A, B, C, Dm;   // step order [a, t1, t2, t3, chi]
+    DT s;             // chi
+};
+
+Split resplit(Step &T, const std::vector<int> &order) {
+    trg_state *S = T.S;
+    Ctx &c = T.c;
+    const int d = (int)S->dims.size();
+    long F = 1;
+    for (int v : S->dims) F *= v;
+    const int chi = S->chi;
+    TRG_REQUIRE(chi <= 64, -6, "bond dimension above 64 not supported by the TSQR kernel");
+    TRG_REQUIRE(F >= chi, -6, "re-split: fewer rows than columns");
+    DT q1 = talloc(c, {(int)F, chi}), r1 = talloc(c, {chi, chi});
+    DT q2 = talloc(c, {(int)F, chi}), r2 = talloc(c, {chi, chi});
+    double *ws = c.ar->dalloc(tsqr_ws_doubles(F, chi));
+    tsqr(S->phi, F, chi, q1.p, r1.p, ws, c.st);
+    tsqr(S->psi, F, chi, q2.p, r2.p, ws, c.st);
+    DT w = contract(c, r1, "ia", r2, "ja", "ij");
+    DT s = talloc(c, {chi}), u = talloc(c, {chi, chi}), v = talloc(c, {chi, chi});
+    svd_rowmajor(T, w, s.p, u.p, v.p);
+    hipLaunchKernelGGL(resplit_norm_kernel, dim3(1), dim3(1), 0, c.st, s.p, chi, S->k, S->dscal, EPS_S, S->dint);
+    DT A = contract(c, q1, "Fa", u, "ab", "Fb");
+    DT Dm = contract(c, q2, "Fa", v, "ab", "Fb");
+    double *sg = c.ar->dalloc(chi);
+    std::vector<int> nd(S->dims.begin(), S->dims.end());
+    sign_vector(A.p, F, chi, chi, nd, pow131(d), sg, c.st);
+    hipLaunchKernelGGL(mask_sign_kernel, dim3(1), dim3(64), 0, c.st, sg, s.p, chi);
+    scale_cols(A.p, F, chi, chi, sg, c.st);
+    scale_cols(Dm.p, F, chi, chi, sg, c.st);
+    // tensors in step order
+    std::string nat, stp;
+    for (int i = 0; i < d; ++i) nat += (char)('a' + i);
+    for (int i = 0; i < d; ++i) stp += (char)('a' + order[i]);
+    nat += 'z';
+    stp += 'z';
+    A.d = nd;
+    A.d.push_back(chi);
+    Dm.d = A.d;
+    Split o;
+    o.A = permuted(c, A, nat, stp);
+    o.Dm = permuted(c, Dm, nat, stp);
+    o.B = talloc(c, o.Dm.d);
+    copy(o.B.p, o.Dm.p, o.Dm.n(), c.st);
+    scale_axis(o.B.p, o.B.d, d, s.p, 1, c.st);
+    o.C = talloc(c, o.A.d);
+    copy(o.C.p, o.A.p, o.A.n(), c.st);
+    scale_axis(o.C.p, o.C.d, d, s.p, 1, c.st);
+    o.s = s;
+    return o;
+}
+
+// ---------------------------------------------------------------- bond swap
+struct Swap {
+    DT X, Y, sig;   // X [alpha, t1.., g], Y [beta, t1.., g], sig [g]
+};
+
+Swap bond_swap(Step &T, const Split &sp) {
+    trg_state *S = T.S;
+    Ctx &c = T.c;
+    const DT &Bt = sp.B, &Ct = sp.C;
+    const int nd = (int)Bt.d.size();   // 1 + (d-1) + 1
+    const int x = Bt.d[0], chi = Bt.d[nd - 1];
+    std::vector<int> td(Bt.d.begin() + 1, Bt.d.end() - 1);
+    long J = 1;
+    for (int v : td) J *= v;
+    const long I = J;
+    const long p = std::min(J, (long)x * chi), q = std::min(I, (long)x * chi);
+    const long rowsN = chi * q, colsN = chi * p;
+    const int gcap = (int)std::min<long>(S->D, std::min(rowsN, colsN));
+    const int m = S->opt.sketch_mult * S->D;
+    const bool exact = S->opt.bond_svd == TRG_SVD_EXACT || m >= std::min(rowsN, colsN);
+    // label strings: x, t legs (i j k / u v w), chi
+    const std::string tl = std::string("ijk").substr(0, td.size());
+    const std::string tu = std::string("uvw").substr(0, td.size());
+    Swap o;
+    o.sig = talloc(c, {gcap});
+    int *kept = T.new_kept();
+    std::vector<int> sdims;   // sign multi-index dims in GPU row order, with their weights
+    if (exact) {
+        const int nb = x * chi;
+        TRG_REQUIRE(nb <= 64 && J >= nb, -6, "exact bond swap: x*chi must be <= 64 and <= prod(transverse)");
+        DT Bp = permuted(c, Bt, "x" + tl + "a", tl + "xa");
+        DT Cp = permuted(c, Ct, "x" + tl + "b", tl + "xb");
+        DT qb = talloc(c, {(int)J, nb}), rb = talloc(c, {nb, nb});
+        DT qc = talloc(c, {(int)I, nb}), rc = talloc(c, {nb, nb});
+        double *ws = c.ar->dalloc(tsqr_ws_doubles(J, nb));
+        tsqr(Bp.p, J, nb, qb.p, rb.p, ws, c.st);
+        tsqr(Cp.p, I, nb, qc.p, rc.p, ws, c.st);
+        rb.d = {nb, x, chi};
+        rc.d = {nb, x, chi};
+        DT N = contract(c, rb, "pxa", rc, "qxb", "aqbp");
+        N.d = {(int)rowsN, (int)colsN};
+        DT s = talloc(c, {(int)colsN}), u = talloc(c, {(int)rowsN, (int)colsN}), v = talloc(c, {(int)colsN, (int)colsN});
+        svd_rowmajor(T, N, s.p, u.p, v.p);
+        kept_count(s.p, (int)colsN, gcap, EPS_S, TAU_DEG, kept, c.st);
+        copy(o.sig.p, s.p, gcap, c.st);
+        hipLaunchKernelGGL(zero_tail_vec_kernel, dim3(1), dim3(256), 0, c.st, o.sig.p, gcap, kept);
+        // U_bond[(alpha, q), g], V_bond[(beta, p), g]: first gcap columns, zero beyond kept
+        DT ub = talloc(c, {chi, (int)q, gcap}), vb = talloc(c, {chi, (int)p, gcap});
+        col_slice(c, u.p, rowsN, colsN, gcap, ub.p);
+        col_slice(c, v.p, colsN, colsN, gcap, vb.p);
+        zero_tail_cols(ub.p, rowsN, gcap, gcap, kept, c.st);
+        zero_tail_cols(vb.p, colsN, gcap, gcap, kept, c.st);
+        DT X = contract(c, ub, "aqg", qc, "iq", "aig");
+        DT Y = contract(c, vb, "bpg", qb, "jp", "bjg");
+        std::vector<int> sd{chi};
+        sd.insert(sd.end(), td.begin(), td.end());
+        double *sg = c.ar->dalloc(gcap);
+        sign_vector(X.p, chi * I, gcap, gcap, sd, pow131((int)sd.size()), sg, c.st);
+        scale_cols(X.p, chi * I, gcap, gcap, sg, c.st);
+        scale_cols(Y.p, chi * J, gcap, gcap, sg, c.st);
+        o.X = X;
+        o.X.d = sd;
+        o.X.d.push_back(gcap);
+        o.Y = Y;
+        o.Y.d = o.X.d;
+        return o;
+    }
+    // ---- randomized SVD of M applied directly (App. A, eq. bond1 / bond2)
+    DT Bp = permuted(c, Bt, "x" + tl + "a", tl + "xa");   // [j, x, alpha]
+    DT Cp = permuted(c, Ct, "x" + tl + "b", tl + "xb");   // [i, x, beta]
+    DT om = talloc(c, {(int)J, chi, m});
+    philox_sketch(om.p, S->opt.seed, S->k, S->opt.instance, td, chi, m, 1, c.st);
+    DT Q = talloc(c, {(int)(I * chi), m}), Qp = talloc(c, {(int)(J * chi), m}), Rp = talloc(c, {m, m}), Rq = talloc(c, {m, m});
+    double *ws = c.ar->dalloc(std::max(tsqr_ws_doubles(I * chi, m), tsqr_ws_doubles(J * chi, m)));
+    DT cur = om;
+    for (int it = 0; it <= S->opt.power_iters; ++it) {
+        // Y[i, alpha, m] = sum_{x, beta} C[x, i, beta] sum_j B[x, j, alpha] Omega[j, beta, m]
+        DT t1;
+        {
+            t1 = talloc(c, {x, chi, chi, m});
+            GemmArgs g{};
+            g.M = chi; g.N = chi * m; g.K = (int)J; g.batch = x;
+            g.A = Bt.p; g.sAr = 1; g.sAk = chi; g.sAb = J * chi;
+            g.B = cur.p; g.sBk = (long)chi * m; g.sBn = 1; g.sBb = 0;
+            g.C = t1.p; g.sCr = (long)chi * m; g.sCn = 1; g.sCb = (long)chi * chi * m;
+            g.alpha = 1.0; g.beta = 0.0;
+            gemm(g, P_FP64, c.st);
+        }
+        DT t1p = permuted(c, t1, "xabm", "xbam");
+        DT y = contract(c, Cp, "ixb", t1p, "xbam", "iam");
+        y.d = {(int)(I * chi), m};
+        tsqr(y.p, I * chi, m, Q.p, Rq.p, ws, c.st);
+        // Yt[j, beta, m] = sum_{x, alpha} B[x, j, alpha] sum_i C[x, i, beta] Q[i, alpha, m]
+        DT t2;
+        {
+            t2 = talloc(c, {x, chi, chi, m});
+            GemmArgs g{};
+            g.M = chi; g.N = chi * m; g.K = (int)I; g.batch = x;
+            g.A = Ct.p; g.sAr = 1; g.sAk = chi; g.sAb = I * chi;
+            g.B = Q.p; g.sBk = (long)chi * m; g.sBn = 1; g.sBb = 0;
+            g.C = t2.p; g.sCr = (long)chi * m; g.sCn = 1; g.sCb = (long)chi * chi * m;
+            g.alpha = 1.0; g.beta = 0.0;
+            gemm(g, P_FP64, c.st);
+        }
+        DT t2p = permuted(c, t2, "xbam", "xabm");
+        DT yt = contract(c, Bp, "jxa", t2p, "xabm", "jbm");
+        yt.d = {(int)(J * chi), m};
+        tsqr(yt.p, J * chi, m, Qp.p, Rp.p, ws, c.st);
+        cur = Qp;
+        cur.d = {(int)J, chi, m};
+    }
+    // SVD of Q^T M = Rp^T Qp^T: Jacobi on Rp^T, whose columns are the rows of Rp
+    DT s = talloc(c, {m}), ut = talloc(c, {m, m}), w = talloc(c, {m, m});
+    svd_colmajor(T, Rp.p, 1, m, m, s.p, ut.p, w.p);
+    kept_count(s.p, m, gcap, EPS_S, TAU_DEG, kept, c.st);
+    copy(o.sig.p, s.p, gcap, c.st);
+    hipLaunchKernelGGL(zero_tail_vec_kernel, dim3(1), dim3(256), 0, c.st, o.sig.p, gcap, kept);
+    // U_bond = Q Ut[:, :gcap] rows (i, alpha); V_bond = Qp W[:, :gcap] rows (j, beta)
+    DT ub = talloc(c, {(int)(I * chi), gcap}), vb = talloc(c, {(int)(J * chi), gcap});
+    {
+        GemmArgs g{};
+        g.M = (int)(I * chi); g.N = gcap; g.K = m; g.batch = 1;
+        g.A = Q.p; g.sAr = m; g.sAk = 1; g.sAb = 0;
+        g.B = ut.p; g.sBk = m; g.sBn = 1; g.sBb = 0;
+        g.C = ub.p; g.sCr = gcap; g.sCn = 1; g.sCb = 0;
+        g.alpha = 1.0; g.beta = 0.0;
+        gemm(g, P_FP64, c.st);
+        g.M = (int)(J * chi); g.A = Qp.p; g.B = w.p; g.C = vb.p;
+        gemm(g, P_FP64, c.st);
+    }
+    zero_tail_cols(ub.p, I * chi, gcap, gcap, kept, c.st);
+    zero_tail_cols(vb.p, J * chi, gcap, gcap, kept, c.st);
+    // sign convention over the multi-index (alpha, i_t1, i_t2, i_t3)
+    std::vector<int> sd(td.begin(), td.end());
+    sd.push_back(chi);
+    std::vector<double> pw;
+    double mlt = 131.0;
+    for (size_t i = 0; i < td.size(); ++i) { pw.push_back(mlt); mlt *= 131.0; }
+    pw.push_back(1.0);
+    double *sg = c.ar->dalloc(gcap);
+    sign_vector(ub.p, I * chi, gcap, gcap, sd, pw, sg, c.st);
+    scale_cols(ub.p, I * chi, gcap, gcap, sg, c.st);
+    scale_cols(vb.p, J * chi, gcap, gcap, sg, c.st);
+    ub.d = td;
+    ub.d.push_back(chi);
+    ub.d.push_back(gcap);
+    vb.d = ub.d;
+    o.X = permuted(c, ub, tl + "ag", "a" + tl + "g");
+    o.Y = permuted(c, vb, tl + "bg", "b" + tl + "g");
+    return o;
+}
+
+// ---------------------------------------------------------------- squeezers
+// K_f, K_b of transverse position pos; tf: top of the upper half [x, t.., alpha],
+// bf: bottom of the upper half [alpha, b.., g] closed through penv on g;
+// tb: top of the lower half [beta, t.., g] closed through oenv; bb: [x, b.., beta].
+void env_grams(Step &T, const DT &tf, const DT &bf, const DT &penv, const DT &tb, const DT &bb, const DT &oenv,
+               int pos, DT &kf, DT &kb) {
+    Ctx &c = T.c;
+    const int nt = (int)tf.d.size() - 2;   // number of transverse legs
+    std::string L = std::string("ijk").substr(0, nt);
+    auto open = [&](char ch) {
+        std::string s = L;
+        s[pos] = ch;
+        return s;
+    };
+    // zt[a, t, A, T] = sum tf[x, .., t, .., a] tf[x, .., T, .., A]
+    DT zt = contract(c, tf, "x" + L + "a", tf, "x" + open('T') + "A", std::string("a") + L[pos] + "AT");
+    DT bp = contract(c, bf, "a" + L + "g", penv, "gh", "a" + L + "h");
+    DT zb = contract(c, bp, "a" + L + "h", bf, "A" + open('B') + "h", std::string("a") + L[pos] + "AB");
+    zt.d = {zt.d[0], zt.d[1], zt.d[2], zt.d[3]};
+    DT k1 = contract(c, zt, "atAT", zb, "abAB", "tbTB");
+    int dt = k1.d[0], db = k1.d[1];
+    kf = k1;
+    kf.d = {dt * db, dt * db};
+    DT yo = contract(c, tb, "b" + L + "g", oenv, "gh", "b" + L + "h");
+    DT zy = contract(c, yo, "b" + L + "h", tb, "B" + open('T') + "h", std::string("b") + L[pos] + "BT");
+    DT zd = contract(c, bb, "x" + L + "b", bb, "x" + open('X') + "B", std::string("b") + L[pos] + "BX");
+    DT k2 = contract(c, zy, "btBT", zd, "bxBX", "txTX");
+    kb = k2;
+    kb.d = {dt * db, dt * db};
+}
+
+// projector pair [dt, db, D]: E (forward) and F (backward)
+void squeezer(Step &T, const DT &kf, const DT &kb, int dt, int db, DT &E, DT &F) {
+    trg_state *S = T.S;
+    Ctx &c = T.c;
+    const int n = dt * db, D = S->D;
+    // eigen-decompositions of K_f and K_b in one batch
+    double *kk = c.ar->dalloc((size_t)2 * n * n);
+    copy(kk, kf.p, (size_t)n * n, c.st);
+    copy(kk + (size_t)n * n, kb.p, (size_t)n * n, c.st);
+    DT lam = talloc(c, {2, n}), vec = talloc(c, {2, n, n});
+    eig_psd(T, kk, 2, n, lam.p, vec.p);
+    DT sq = talloc(c, {2, n});
+    hipLaunchKernelGGL(sqrt_clamp_kernel, dim3(g1(n)), dim3(256), 0, c.st, lam.p, sq.p, n, EPS_LAM);
+    hipLaunchKernelGGL(sqrt_clamp_kernel, dim3(g1(n)), dim3(256), 0, c.st, lam.p + n, sq.p + n, n, EPS_LAM);
+    DT wf{vec.p, {n, n}}, wb{vec.p + (size_t)n * n, {n, n}};
+    // R_f R_b^T = diag(sqf) Wf^T Wb diag(sqb)
+    DT g = contract(c, wf, "pi", wb, "pj", "ij");
+    scale_axis(g.p, g.d, 0, sq.p, 1, c.st);
+    scale_axis(g.p, g.d, 1, sq.p + n, 1, c.st);
+    DT s = talloc(c, {n}), u = talloc(c, {n, n}), v = talloc(c, {n, n});
+    svd_rowmajor(T, g, s.p, u.p, v.p);
+    int *kept = T.new_kept();
+    kept_count(s.p, n, D, EPS_SQ, TAU_DEG, kept, c.st);
+    DT is = talloc(c, {n});
+    hipLaunchKernelGGL(isqrt_kept_kernel, dim3(g1(n)), dim3(256), 0, c.st, s.p, is.p, n, kept);
+    // E = Wb diag(sqb) V[:, :D] S^-1/2 ; F = Wf diag(sqf) U[:, :D] S^-1/2
+    DT vd = talloc(c, {n, D}), ud = talloc(c, {n, D});
+    {
+        GemmArgs ga{};
+        ga.M = n; ga.N = D; ga.K = n; ga.batch = 1;
+        ga.A = wb.p; ga.sAr = n; ga.sAk = 1;
+        ga.B = v.p; ga.sBk = n; ga.sBn = 1;
+        ga.C = vd.p; ga.sCr = D; ga.sCn = 1;
+        ga.alpha = 1.0;
+        // scale rows of V by sqb first: V' = diag(sqb) V
+        DT vs = talloc(c, {n, n});
+        copy(vs.p, v.p, (size_t)n * n, c.st);
+        scale_axis(vs.p, vs.d, 0, sq.p + n, 1, c.st);
+        ga.B = vs.p;
+        gemm(ga, P_FP64, c.st);
+        DT us = talloc(c, {n, n});
+        copy(us.p, u.p, (size_t)n * n, c.st);
+        scale_axis(us.p, us.d, 0, sq.p, 1, c.st);
+        ga.A = wf.p; ga.B = us.p; ga.C = ud.p;
+        gemm(ga, P_FP64, c.st);
+    }
+    scale_axis(vd.p, vd.d, 1, is.p, 1, c.st);
+    scale_axis(ud.p, ud.d, 1, is.p, 1, c.st);
+    double *sg = c.ar->dalloc(D);
+    sign_vector(vd.p, n, D, D, {dt, db}, {1.0, 131.0}, sg, c.st);
+    scale_cols(vd.p, n, D, D, sg, c.st);
+    scale_cols(ud.p, n, D, D, sg, c.st);
+    E = vd;
+    E.d = {dt, db, D};
+    F = ud;
+    F.d = {dt, db, D};
+}
+
+void identity_squeezer(Step &T, int dt, int db, DT &E, DT &F) {
+    int n = dt * db;
+    E = talloc(T.c, {dt, db, n});
+    hipLaunchKernelGGL(eye_kernel, dim3(g1((long)n * n)), dim3(256), 0, T.c.st, E.p, n);
+    F = E;
+}
+
+// ---------------------------------------------------------------- ATRG (d = 4)
+void atrg_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi) {
+    Ctx &c = T.c;
+    const int D = T.S->D;
+    const DT &A = sp.A, &Dm = sp.Dm;
+    DT Xs = talloc(c, sw.X.d);
+    copy(Xs.p, sw.X.p, Xs.n(), c.st);
+    scale_axis(Xs.p, Xs.d, 4, sw.sig.p, 1, c.st);
+    const int ng = sw.sig.d[0];
+    DT pe = talloc(c, {ng, ng});
+    hipLaunchKernelGGL(eye_kernel, dim3(g1((long)ng * ng)), dim3(256), 0, c.st, pe.p, ng);
+    DT s2 = talloc(c, {ng});
+    hipLaunchKernelGGL(square_kernel, dim3(g1(ng)), dim3(256), 0, c.st, sw.sig.p, s2.p, ng);
+    DT oe = talloc(c, {ng, ng});
+    copy(oe.p, pe.p, (size_t)ng * ng, c.st);
+    scale_axis(oe.p, oe.d, 0, s2.p, 1, c.st);
+    DT E[3], F[3];
+    for (int pos = 0; pos < 3; ++pos) {
+        int dt = A.d[pos + 1], db = sw.X.d[pos + 1];
+        if (dt * db <= D) {
+            identity_squeezer(T, dt, db, E[pos], F[pos]);
+        } else {
+            DT kf, kb;
+            env_grams(T, A, Xs, pe, sw.Y, Dm, oe, pos, kf, kb);
+            squeezer(T, kf, kb, dt, db, E[pos], F[pos]);
+        }
+    }
+    // makeG: G[x, k1, k2, k3, g] = A X sigma E1 E2 E3 (pairwise, as in the oracle)
+    DT t = contract(c, A, "xijka", E[0], "iIp", "xjkaIp");
+    t = contract(c, t, "xjkaIp", Xs, "aIJKg", "xjkpJKg");
+    t = contract(c, t, "xjkpJKg", E[1], "jJq", "xkpKgq");
+    phi = contract(c, t, "xkpKgq", E[2], "kKr", "xpqrg");
+    DT u = contract(c, Dm, "xIJKb", F[0], "iIp", "xJKbip");
+    u = contract(c, u, "xJKbip", sw.Y, "bijkg", "xJKpjkg");
+    u = contract(c, u, "xJKpjkg", F[1], "jJq", "xKpkgq");
+    psi = contract(c, u, "xKpkgq", F[2], "kKr", "xpqrg");
+}
+
+// ---------------------------------------------------------------- triad-ATRG
+void triad_iso(Step &T, const DT &gram, int d1, int d2, int rcap, DT &U) {
+    Ctx &c = T.c;
+    const int n = d1 * d2;
+    if (n <= rcap) {
+        U = talloc(c, {d1, d2, n});
+        hipLaunchKernelGGL(eye_kernel, dim3(g1((long)n * n)), dim3(256), 0, c.st, U.p, n);
+        return;
+    }
+    DT lam = talloc(c, {n}), vec = talloc(c, {n, n});
+    eig_psd(T, gram.p, 1, n, lam.p, vec.p);
+    int *kept = T.new_kept();
+    kept_count(lam.p, n, rcap, EPS_LAM, TAU_DEG, kept, c.st);
+    U = talloc(c, {n, rcap});
+    col_slice(c, vec.p, n, n, rcap, U.p);
+    zero_tail_cols(U.p, n, rcap, rcap, kept, c.st);
+    double *sg = c.ar->dalloc(rcap);
+    sign_vector(U.p, n, rcap, rcap, {d1, d2}, {1.0, 131.0}, sg, c.st);
+    scale_cols(U.p, n, rcap, rcap, sg, c.st);
+    U.d = {d1, d2, rcap};
+}
+
+void triad_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi) {
+    trg_state *S = T.S;
+    Ctx &c = T.c;
+    const int D = S->D;
+    const DT &A = sp.A, &Dm = sp.Dm, &X = sw.X, &Y = sw.Y;
+    const int d1 = A.d[1], d2 = A.d[2], d3 = A.d[3];
+    const int rcap = std::min(S->opt.r * D, d1 * d2);
+    const int ng = sw.sig.d[0];
+    DT s2 = talloc(c, {ng});
+    hipLaunchKernelGGL(square_kernel, dim3(g1(ng)), dim3(256), 0, c.st, sw.sig.p, s2.p, ng);
+    DT Xs2 = talloc(c, X.d), Ys2 = talloc(c, Y.d);
+    copy(Xs2.p, X.p, X.n(), c.st);
+    scale_axis(Xs2.p, Xs2.d, 4, s2.p, 1, c.st);
+    copy(Ys2.p, Y.p, Y.n(), c.st);
+    scale_axis(Ys2.p, Ys2.d, 4, s2.p, 1, c.st);
+    // triad Grams (eq. HOSVD)
+    DT xsx = contract(c, Xs2, "aijtg", X, "bijtg", "ab");
+    DT ysy = contract(c, Ys2, "aijtg", Y, "bijtg", "ab");
+    DT ax = contract(c, A, "xijta", xsx, "ab", "xijtb");
+    DT ga = contract(c, ax, "xijtb", A, "xkltb", "ijkl");
+    DT gx = contract(c, Xs2, "aijtg", X, "akltg", "ijkl");
+    DT gy = contract(c, Ys2, "aijtg", Y, "akltg", "ijkl");
+    DT dy = contract(c, Dm, "xijta", ysy, "ab", "xijtb");
+    DT gd = contract(c, dy, "xijtb", Dm, "xkltb", "ijkl");
+    DT UA, UX, UY, UD;
+    triad_iso(T, ga, d1, d2, rcap, UA);
+    triad_iso(T, gx, d1, d2, rcap, UX);
+    triad_iso(T, gy, d1, d2, rcap, UY);
+    triad_iso(T, gd, d1, d2, rcap, UD);
+    // triad tensors
+    DT e = contract(c, A, "xijta", UA, "ijk", "xkta");
+    DT f = contract(c, X, "aijtg", UX, "ijk", "aktg");
+    scale_axis(f.p, f.d, 3, sw.sig.p, 1, c.st);
+    DT g = contract(c, Y, "bijtg", UY, "ijk", "bktg");
+    DT hh = contract(c, Dm, "xijtb", UD, "ijk", "xktb");
+    // O and P (Gram matrices of the upper and lower blocks)
+    DT ee = contract(c, e, "xkta", e, "xktb", "ab");
+    DT ef = contract(c, ee, "ab", f, "bktg", "aktg");
+    DT o = contract(c, ef, "aktg", f, "akth", "gh");
+    DT h2 = contract(c, hh, "xktb", hh, "xktc", "bc");
+    DT hg = contract(c, h2, "bc", g, "cktg", "bktg");
+    DT p = contract(c, hg, "bktg", g, "bkth", "gh");
+    // projected A, X sigma, Y, D
+    DT at = contract(c, e, "xkta", UA, "ijk", "xijta");
+    DT xt = contract(c, f, "aktg", UX, "ijk", "aijtg");
+    DT yt = contract(c, g, "bktg", UY, "ijk", "bijtg");
+    DT dt = contract(c, hh, "xktb", UD, "ijk", "xijtb");
+    DT M[3], N[3];
+    const int dd[3] = {d1, d2, d3};
+    for (int pos = 0; pos < 3; ++pos) {
+        if (dd[pos] * dd[pos] <= D) {
+            identity_squeezer(T, dd[pos], dd[pos], M[pos], N[pos]);
+        } else {
+            DT kf, kb;
+            env_grams(T, at, xt, p, yt, dt, o, pos, kf, kb);
+            squeezer(T, kf, kb, dd[pos], dd[pos], M[pos], N[pos]);
+        }
+    }
+    // makeMG: Phi = (E F M3)(I J M1 M2)
+    DT em = contract(c, e, "xAta", M[2], "tsc", "xAasc");
+    DT efm = contract(c, em, "xAasc", f, "aXsg", "xAXcg", c.prec);
+    DT im = contract(c, UA, "ijA", M[0], "ipk", "jApk");
+    DT imm = contract(c, im, "jApk", M[1], "jql", "Apkql");
+    DT ijmm = contract(c, imm, "Apkql", UX, "pqX", "AXkl");
+    phi = contract(c, efm, "xAXcg", ijmm, "AXkl", "xklcg", c.prec);
+    // makeMH: Psi = (G H N3)(K L N1 N2)
+    DT hn = contract(c, hh, "xDsb", N[2], "tsc", "xDbtc");
+    DT ghn = contract(c, g, "bYtg", hn, "xDbtc", "xYDcg", c.prec);
+    DT kn = contract(c, UY, "ijY", N[0], "ipk", "jYpk");
+    DT knn = contract(c, kn, "jYpk", N[1], "jql", "Ypkql");
+    DT klnn = contract(c, knn, "Ypkql", UD, "pqD", "YDkl");
+    psi = contract(c, ghn, "xYDcg", klnn, "YDkl", "xklcg", c.prec);
+}
+
+// ---------------------------------------------------------------- one step
+void do_step(trg_state *S, int axis, bool triad) {
+    TRG_REQUIRE(S->init, -2, "step before tensor_init");
+    const int d = S->opt.dim;
+    TRG_REQUIRE(axis >= 0 && axis < d, -1, "axis out of range");
+    TRG_REQUIRE(d == 4, -6, "the GPU path implements d = 4");
+    S->ar.reset();
+    Step T(S);
+    std::vector<int> order(d);
+    for (int i = 0; i < d; ++i) order[i] = (axis + i) % d;
+    Split sp = resplit(T, order);
+    Swap sw = bond_swap(T, sp);
+    DT phi, psi;
+    if (triad) triad_coarse(T, sp, sw, phi, psi);
+    else atrg_coarse(T, sp, sw, phi, psi);
+    // back to natural axis order
+    std::string stp, nat;
+    for (int i = 0; i < d; ++i) stp += (char)('a' + order[i]);
+    for (int i = 0; i < d; ++i) nat += (char)('a' + i);
+    stp += 'z';
+    nat += 'z';
+    TRG_REQUIRE((size_t)phi.n() <= S->cap_state && (size_t)psi.n() <= S->cap_state, -6, "state exceeds D^5");
+    std::vector<int> perm(d + 1);
+    for (int i = 0; i <= d; ++i) perm[i] = (int)stp.find(nat[i]);
+    permute(phi.p, S->phi, phi.d, perm, S->st);
+    permute(psi.p, S->psi, psi.d, perm, S->st);
+    std::vector<int> nd(d);
+    for (int i = 0; i < d; ++i) nd[i] = phi.d[perm[i]];
+    S->dims = nd;
+    S->chi = phi.d[d];
+    S->sigma_last.assign(sw.sig.d[0], 0.0);
+    TRG_HIP_CHECK(hipMemcpyAsync(S->sigma_last.data(), sw.sig.p, sizeof(double) * sw.sig.d[0], hipMemcpyDeviceToHost, S->st));
+    TRG_HIP_CHECK(hipStreamSynchronize(S->st));
+    S->k += 1;
+}
+
+}  // namespace
+}  // namespace trg
+
+// ====================================================================== C ABI
+using trg::Error;
+
+namespace {
+int fail(trg_state *s, const Error &e) {
+    if (s) s->err = e.what();
+    return e.code;
+}
+int fail_std(trg_state *s, const std::exception &e) {
+    if (s) s->err = e.what();
+    return TRG_E_HIP;
+}
+struct DevGuard {
+    int prev = -1;
+    explicit DevGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (hipSetDevice(dev) != hipSuccess) throw Error(TRG_E_HIP, "hipSetDevice failed");
+    }
+    ~DevGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+thread_local std::string g_err;
+}  // namespace
+
+extern "C" {
+
+void trg_default_options(trg_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->dim = 4;
+    o->r = 7;
+    o->sketch_mult = 2;
+    o->power_iters = 1;
+    o->precision = TRG_FP64;
+    o->bond_svd = TRG_SVD_SKETCH;
+    o->max_sweeps = 60;
+}
+
+int trg_create(const trg_options *opt, trg_state **out) {
+    if (!out) return TRG_E_INVALID;
+    *out = nullptr;
+    if (!opt) return TRG_E_INVALID;
+    if (opt->dim != 4 || opt->r < 1 || opt->sketch_mult < 1 || opt->power_iters < 0 ||
+        (opt->precision < 0 || opt->precision > 2) || (opt->bond_svd != 0 && opt->bond_svd != 1))
+        return TRG_E_INVALID;
+    trg_state *s = new (std::nothrow) trg_state();
+    if (!s) return TRG_E_NOMEM;
+    s->opt = *opt;
+    try {
+        DevGuard g(opt->device);
+        s->st = static_cast<hipStream_t>(opt->stream);
+        s->ar.set_cap(opt->workspace_cap);
+        TRG_HIP_CHECK(hipMalloc(&s->dscal, 64 * sizeof(double)));
+        TRG_HIP_CHECK(hipMalloc(&s->dint, 256 * sizeof(int)));
+    } catch (const Error &e) {
+        g_err = e.what();
+        trg_destroy(s);
+        return e.code;
+    }
+    *out = s;
+    return TRG_OK;
+}
+
+int trg_destroy(trg_state *s) {
+    if (!s) return TRG_OK;
+    (void)hipSetDevice(s->opt.device);
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    else (void)hipDeviceSynchronize();
+    if (s->phi) (void)hipFree(s->phi);
+    if (s->psi) (void)hipFree(s->psi);
+    if (s->dscal) (void)hipFree(s->dscal);
+    if (s->dint) (void)hipFree(s->dint);
+    delete s;
+    return TRG_OK;
+}
+
+int tensor_init(trg_state *s, int model, double beta, double h, int D) {
+    if (!s) return TRG_E_INVALID;
+    if (model != TRG_MODEL_ISING || !(beta >= 0.0) || !std::isfinite(beta) || !std::isfinite(h) || D < 2)
+        return TRG_E_INVALID;
+    try {
+        DevGuard g(s->opt.device);
+        const int d = s->opt.dim;
+        size_t cap = 1;
+        for (int i = 0; i <= d; ++i) cap *= (size_t)std::max(D, 2);
+        if (cap > s->cap_state) {
+            if (s->phi) (void)hipFree(s->phi);
+            if (s->psi) (void)hipFree(s->psi);
+            s->phi = s->psi = nullptr;
+            TRG_HIP_CHECK(hipMalloc(&s->phi, cap * sizeof(double)));
+            TRG_HIP_CHECK(hipMalloc(&s->psi, cap * sizeof(double)));
+            s->cap_state = cap;
+        }
+        // CP form: Phi[i_1..i_d, a] = e^{h s_a} prod W[a, i_mu], Psi = prod W[a, j_mu]
+        const double cb = std::sqrt(std::cosh(beta)), sb = std::sqrt(std::sinh(beta));
+        const double w[2][2] = {{cb, sb}, {cb, -sb}};
+        const int F = 1 << d;
+        std::vector<double> phi(F * 2), psi(F * 2);
+        for (int a = 0; a < 2; ++a) {
+            double fa = std::exp(h * (a == 0 ? 1.0 : -1.0));
+            for (int idx = 0; idx < F; ++idx) {
+                double prod = 1.0;
+                for (int mu = 0; mu < d; ++mu) prod *= w[a][(idx >> (d - 1 - mu)) & 1];
+                psi[idx * 2 + a] = prod;
+                phi[idx * 2 + a] = fa * prod;
+            }
+        }
+        hipStream_t st = s->st;
+        TRG_HIP_CHECK(hipMemcpyAsync(s->phi, phi.data(), phi.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        TRG_HIP_CHECK(hipMemcpyAsync(s->psi, psi.data(), psi.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        double zero[2] = {0.0, 0.0};
+        int izero[1] = {0};
+        TRG_HIP_CHECK(hipMemcpyAsync(s->dscal, zero, sizeof(zero), hipMemcpyHostToDevice, st));
+        TRG_HIP_CHECK(hipMemcpyAsync(s->dint, izero, sizeof(izero), hipMemcpyHostToDevice, st));
+        TRG_HIP_CHECK(hipStreamSynchronize(st));
+        s->dims.assign(d, 2);
+        s->chi = 2;
+        s->D = D;
+        s->beta = beta;
+        s->h = h;
+        s->k = 0;
+        s->init = true;
+        s->sigma_last.clear();
+    } catch (const Error &e) {
+        return fail(s, e);
+    } catch (const std::exception &e) {
+        return fail_std(s, e);
+    }
+    return TRG_OK;
+}
+
+static int step_common(trg_state *s, int axis, bool triad) {
+    if (!s) return TRG_E_INVALID;
+    if (!s->init) {
+        s->err = "step before tensor_init";
+        return TRG_E_STATE;
+    }
+    if (axis < 0 || axis >= s->opt.dim) {
+        s->err = "axis out of range";
+        return TRG_E_INVALID;
+    }
+    if (triad && s->opt.dim != 4) {
+        s->err = "triad-ATRG needs dim 4";
+        return TRG_E_INVALID;
+    }
+    try {
+        DevGuard g(s->opt.device);
+        trg::do_step(s, axis, triad);
+    } catch (const Error &e) {
+        return fail(s, e);
+    } catch (const std::exception &e) {
+        return fail_std(s, e);
+    }
+    return TRG_OK;
+}
+
+int atrg_step(trg_state *s, int axis) { return step_common(s, axis, false); }
+int triad_atrg_step(trg_state *s, int axis) { return step_common(s, axis, true); }
+
+int log_z_per_site(trg_state *s, double *out) {
+    if (!s || !out) return TRG_E_INVALID;
+    if (!s->init) return TRG_E_STATE;
+    try {
+        DevGuard g(s->opt.device);
+        long n = (long)s->chi;
+        for (int v : s->dims) n *= v;
+        double *part = static_cast<double *>(s->ar.alloc(1024 * sizeof(double)));
+        hipLaunchKernelGGL(trg::dot_partial_kernel, dim3(1024), dim3(256), 0, s->st, s->phi, s->psi, n, part);
+        hipLaunchKernelGGL(trg::sum_kernel, dim3(1), dim3(256), 0, s->st, part, 1024, s->dscal + 1);
+        double hs[2];
+        int status = 0;
+        TRG_HIP_CHECK(hipMemcpyAsync(hs, s->dscal, sizeof(hs), hipMemcpyDeviceToHost, s->st));
+        TRG_HIP_CHECK(hipMemcpyAsync(&status, s->dint, sizeof(int), hipMemcpyDeviceToHost, s->st));
+        TRG_HIP_CHECK(hipStreamSynchronize(s->st));
+        if (status != 0) throw Error(TRG_E_NUMERICAL, "non-positive or non-finite norm at a re-split");
+        if (!(hs[1] > 0.0) || !std::isfinite(hs[1])) throw Error(TRG_E_NUMERICAL, "final trace is not positive");
+        *out = hs[0] + std::ldexp(std::log(hs[1]), -s->k);
+    } catch (const Error &e) {
+        return fail(s, e);
+    } catch (const std::exception &e) {
+        return fail_std(s, e);
+    }
+    return TRG_OK;
+}
+
+int trg_shape(trg_state *s, int *dims, int *chi, int *steps) {
+    if (!s) return TRG_E_INVALID;
+    if (!s->init) return TRG_E_STATE;
+    if (dims)
+        for (size_t i = 0; i < s->dims.size(); ++i) dims[i] = s->dims[i];
+    if (chi) *chi = s->chi;
+    if (steps) *steps = s->k;
+    return TRG_OK;
+}
+
+size_t trg_export_size(trg_state *s, int which) {
+    if (!s || !s->init) return 0;
+    size_t n = (size_t)s->chi;
+    for (int v : s->dims) n *= v;
+    if (which == TRG_T_PHI || which == TRG_T_PSI) return n * sizeof(double);
+    if (which == TRG_T_SIGMA) return s->sigma_last.size() * sizeof(double);
+    return 0;
+}
+
+int trg_export(trg_state *s, int which, void *dst, size_t bytes) {
+    if (!s || !dst) return TRG_E_INVALID;
+    if (!s->init) return TRG_E_STATE;
+    size_t need = trg_export_size(s, which);
+    if (need == 0 || bytes != need) return TRG_E_INVALID;
+    try {
+        DevGuard g(s->opt.device);
+        if (which == TRG_T_SIGMA) {
+            std::memcpy(dst, s->sigma_last.data(), need);
+            return TRG_OK;
+        }
+        const double *src = which == TRG_T_PHI ? s->phi : s->psi;
+        TRG_HIP_CHECK(hipMemcpyAsync(dst, src, need, hipMemcpyDeviceToHost, s->st));
+        TRG_HIP_CHECK(hipStreamSynchronize(s->st));
+    } catch (const Error &e) {
+        return fail(s, e);
+    }
+    return TRG_OK;
+}
+
+int trg_set_timing(trg_state *s, int enable) {
+    if (!s) return TRG_E_INVALID;
+    s->timing = enable != 0;
+    return TRG_OK;
+}
+
+int trg_kernel_time(trg_state *s, double *ms, double *flops, int *launches) {
+    if (!s) return TRG_E_INVALID;
+    if (ms) *ms = s->t_ms;
+    if (flops) *flops = s->t_flops;
+    if (launches) *launches = s->t_launch;
+    s->t_ms = s->t_flops = 0.0;
+    s->t_launch = 0;
+    return TRG_OK;
+}
+
+const char *trg_strerror(int code) {
+    switch (code) {
+        case TRG_OK: return "ok";
+        case TRG_E_INVALID: return "invalid argument";
+        case TRG_E_STATE: return "state not initialised";
+        case TRG_E_NOMEM: return "out of device memory or workspace cap";
+        case TRG_E_NUMERICAL: return "numerical failure";
+        case TRG_E_HIP: return "HIP runtime error";
+        case TRG_E_UNSUPPORTED: return "unsupported shape";
+        default: return "unknown error";
+    }
+}
+
+const char *trg_last_error(trg_state *s) { return s ? s->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"
+
+// ====================================================================== self-tests
+namespace {
+struct Scratch {
+    trg::Arena ar;
+    trg::Ctx c;
+    Scratch() {
+        c.st = nullptr;
+        c.ar = &ar;
+        c.prec = trg::P_FP64;
+    }
+    double *up(const double *h, size_t n) {
+        double *d = ar.dalloc(n);
+        TRG_HIP_CHECK(hipMemcpy(d, h, n * sizeof(double), hipMemcpyHostToDevice));
+        return d;
+    }
+    void down(double *h, const double *d, size_t n) {
+        TRG_HIP_CHECK(hipMemcpy(h, d, n * sizeof(double), hipMemcpyDeviceToHost));
+    }
+};
+}  // namespace
+
+extern "C" {
+
+int trg_selftest_gemm(int precision, int ta, int tb, int M, int N, int K, int batch, const double *A,
+                      const double *B, double *C) {
+    if (!A || !B || !C || M < 1 || N < 1 || K < 0 || batch < 1 || precision < 0 || precision > 2)
+        return TRG_E_INVALID;
+    try {
+        Scratch s;
+        size_t na = (size_t)M * K * batch, nb = (size_t)K * N * batch, nc = (size_t)M * N * batch;
+        double *a = s.up(A, std::max<size_t>(na, 1)), *b = s.up(B, std::max<size_t>(nb, 1));
+        double *c = s.ar.dalloc(nc);
+        trg::GemmArgs g{};
+        g.M = M; g.N = N; g.K = K; g.batch = batch;
+        g.A = a; g.sAr = ta ? 1 : K; g.sAk = ta ? M : 1; g.sAb = (long)M * K;
+        g.B = b; g.sBk = tb ? 1 : N; g.sBn = tb ? K : 1; g.sBb = (long)K * N;
+        g.C = c; g.sCr = N; g.sCn = 1; g.sCb = (long)M * N;
+        g.alpha = 1.0; g.beta = 0.0;
+        if (K == 0) trg::fill(c, nc, 0.0, nullptr);
+        else trg::gemm(g, (trg::Prec)precision, nullptr);
+        s.down(C, c, nc);
+    } catch (const Error &e) {
+        g_err = e.what();
+        return e.code;
+    }
+    return TRG_OK;
+}
+
+int trg_selftest_tsqr(int m, int n, const double *A, double *Q, double *R) {
+    if (!A || !Q || !R || n < 1 || m < n) return TRG_E_INVALID;
+    try {
+        Scratch s;
+        double *a = s.up(A, (size_t)m * n);
+        double *q = s.ar.dalloc((size_t)m * n), *r = s.ar.dalloc((size_t)n * n);
+        double *ws = s.ar.dalloc(trg::tsqr_ws_doubles(m, n));
+        trg::tsqr(a, m, n, q, r, ws, nullptr);
+        s.down(Q, q, (size_t)m * n);
+        s.down(R, r, (size_t)n * n);
+    } catch (const Error &e) {
+        g_err = e.what();
+        return e.code;
+    }
+    return TRG_OK;
+}
+
+int trg_selftest_svd(int m, int n, const double *A, double *U, double *S, double *V, int *sweeps) {
+    if (!A || !U || !S || !V || n < 1 || m < n) return TRG_E_INVALID;
+    try {
+        Scratch s;
+        std::vector<double> at((size_t)m * n);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j) at[(size_t)j * m + i] = A[(size_t)i * n + j];
+        double *ut = s.up(at.data(), at.size());
+        double *vt = s.ar.dalloc((size_t)n * n), *work = s.ar.dalloc((size_t)n + 1);
+        double *sv = s.ar.dalloc(n), *us = s.ar.dalloc((size_t)m * n), *vs = s.ar.dalloc((size_t)n * n);
+        int *flags = static_cast<int *>(s.ar.alloc(64 * sizeof(int)));
+        trg::JacobiBatch jb{1, m, n, ut, vt, (long)m * n, (long)n * n};
+        int sw = trg::jacobi_svd(jb, 80, flags, work, nullptr);
+        trg::jacobi_finish(jb, sv, us, vs, work, nullptr);
+        s.down(U, us, (size_t)m * n);
+        s.down(S, sv, n);
+        s.down(V, vs, (size_t)n * n);
+        if (sweeps) *sweeps = sw;
+    } catch (const Error &e) {
+        g_err = e.what();
+        return e.code;
+    }
+    return TRG_OK;
+}
+
+int trg_selftest_sketch(uint64_t seed, int step, uint32_t instance, int chi, int j1, int j2, int j3, int m,
+                        double *out) {
+    if (!out || chi < 1 || j1 < 1 || j2 < 1 || j3 < 1 || m < 1) return TRG_E_INVALID;
+    try {
+        Scratch s;
+        size_t n = (size_t)chi * j1 * j2 * j3 * m;
+        double *o = s.ar.dalloc(n);
+        trg::philox_sketch(o, seed, step, instance, {j1, j2, j3}, chi, m, 0, nullptr);
+        s.down(out, o, n);
+    } catch (const Error &e) {
+        g_err = e.what();
+        return e.code;
+    }
+    return TRG_OK;
+}
+
+}  // extern "C"

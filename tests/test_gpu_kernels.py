@@ -1,0 +1,90 @@
+"""GPU kernels of the path against numpy and the oracle (through the C ABI)."""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2507_21909_amd as trg
+from oracle.philox import sketch_omega
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("shape", [(1, 16, 16, 4), (3, 67, 45, 33), (2, 130, 70, 129), (1, 1, 200, 17),
+                                   (5, 64, 64, 64), (1, 300, 1, 7)])
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+def test_gemm_f64(shape, ta, tb):
+    batch, m, n, k = shape
+    _say("gemm f64", shape, ta, tb)
+    rng = np.random.default_rng(m * n + k)
+    a = rng.standard_normal((batch, k, m) if ta else (batch, m, k))
+    b = rng.standard_normal((batch, n, k) if tb else (batch, k, n))
+    c = trg.selftest_gemm(a, b, ta, tb)
+    aa = np.swapaxes(a, 1, 2) if ta else a
+    bb = np.swapaxes(b, 1, 2) if tb else b
+    ref = aa @ bb
+    assert np.max(np.abs(c - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))) * np.sqrt(k)
+
+
+@pytest.mark.parametrize("m,n", [(4, 4), (37, 5), (256, 64), (1000, 33), (5000, 64), (70000, 17), (300000, 2)])
+def test_tsqr(m, n):
+    _say("tsqr", m, n)
+    rng = np.random.default_rng(m + n)
+    a = rng.standard_normal((m, n)) * (10.0 ** -np.linspace(0, 8, n))[None, :]
+    q, r = trg.selftest_tsqr(a)
+    assert np.max(np.abs(q @ r - a)) < 1e-13 * np.max(np.abs(a))
+    assert np.max(np.abs(q.T @ q - np.eye(n))) < 1e-13
+    assert np.all(np.diagonal(r) >= 0)
+    assert np.allclose(np.tril(r, -1), 0)
+    # unique QR (full column rank): matches LAPACK up to column signs
+    q2, r2 = np.linalg.qr(a)
+    sg = np.sign(np.diagonal(r2))
+    assert np.max(np.abs(r - r2 * sg[:, None])) < 1e-12 * np.max(np.abs(r))
+
+
+def test_tsqr_rank_deficient():
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((3000, 4)) @ rng.standard_normal((4, 12))
+    q, r = trg.selftest_tsqr(a)
+    assert np.max(np.abs(q @ r - a)) < 1e-12 * np.max(np.abs(a))
+    assert np.max(np.abs(q.T @ q - np.eye(12))) < 1e-12
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (8, 8), (64, 64), (40, 17), (200, 120), (300, 300)])
+def test_jacobi_svd(m, n):
+    _say("svd", m, n)
+    rng = np.random.default_rng(m * 7 + n)
+    a = rng.standard_normal((m, n))
+    u, s, v, sweeps = trg.selftest_svd(a)
+    ref = np.linalg.svd(a, compute_uv=False)
+    assert np.max(np.abs(s - ref)) < 1e-13 * ref[0] * np.sqrt(n)
+    assert np.max(np.abs(u @ np.diag(s) @ v.T - a)) < 1e-13 * ref[0] * np.sqrt(n)
+    assert np.max(np.abs(v.T @ v - np.eye(n))) < 1e-13 * np.sqrt(n)
+    assert sweeps < 40
+
+
+def test_jacobi_svd_graded_psd_eigen():
+    rng = np.random.default_rng(9)
+    n = 150
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = 10.0 ** -np.linspace(0, 12, n)
+    k = (q * lam) @ q.T
+    k = 0.5 * (k + k.T)
+    _u, s, v, _ = trg.selftest_svd(k)
+    assert np.max(np.abs(s - lam) / lam[0]) < 1e-13
+    # leading eigenvectors (well separated) match up to sign
+    for j in range(10):
+        assert abs(abs(v[:, j] @ q[:, j]) - 1.0) < 1e-10
+
+
+def test_sketch_matches_oracle():
+    _say("sketch")
+    g = trg.selftest_sketch(0x2507219090000000, 5, 3, 7, (5, 4, 3), 9)
+    o = sketch_omega(0x2507219090000000, 5, 3, 7, (5, 4, 3), 9)
+    assert g.shape == o.shape
+    assert np.max(np.abs(g - o)) < 1e-13
