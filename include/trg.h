@@ -45,7 +45,8 @@ extern "C" {
 
 #define TRG_FP64   0   /* every contraction in FP64 (MFMA f64)                                     */
 #define TRG_FP32   1   /* coarse-graining contractions (makeMG/makeMH) in FP32 MFMA; rest FP64     */
-#define TRG_BF16X3 2   /* coarse-graining contractions as 3-way split BF16 MFMA, FP32 accumulate   */
+#define TRG_BF16X3 2   /* coarse-graining contractions as split BF16 MFMA, 3 products, FP32 acc.   */
+#define TRG_BF16X6 3   /* same with the 6 split products i + j <= 2 (about FP32 accuracy)          */
 
 #define TRG_SVD_SKETCH 0  /* bond swap by the randomized SVD of App. A (power_iters passes)         */
 #define TRG_SVD_EXACT  1  /* bond swap by the exact SVD of the QR-reduced core of App. A            */
@@ -57,7 +58,7 @@ typedef struct trg_options {
     int power_iters;    /* extra power passes of the randomized SVD (App. A loop count q = this+1) */
     uint64_t seed;      /* Philox4x32-10 key of the Gaussian sketch                                */
     uint32_t instance;  /* Philox counter word 2 (distinguishes independent solves)                */
-    int precision;      /* TRG_FP64 / TRG_FP32 / TRG_BF16X3                                        */
+    int precision;      /* TRG_FP64 / TRG_FP32 / TRG_BF16X3 / TRG_BF16X6                           */
     int bond_svd;       /* TRG_SVD_SKETCH / TRG_SVD_EXACT                                          */
     int max_sweeps;     /* Jacobi sweep limit (0: default 60)                                       */
     size_t workspace_cap; /* bytes of device workspace the state may hold (0: unlimited)           */
@@ -148,7 +149,7 @@ const char *trg_last_error(trg_state *s);
 
 /* C[b] = A[b] op B[b] in FP64 MFMA: A (M x K, or K x M if ta), B (K x N, or
  * N x K if tb), C (M x N), batch b with strides M*K, K*N, M*N.  precision
- * selects FP64 / FP32 / BF16X3 arithmetic. */
+ * selects FP64 / FP32 / BF16X3 / BF16X6 arithmetic. */
 int trg_selftest_gemm(int precision, int ta, int tb, int M, int N, int K, int batch,
                       const double *A, const double *B, double *C);
 

@@ -11,7 +11,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtrg.so")
 
-FP64, FP32, BF16X3 = 0, 1, 2
+FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 SVD_SKETCH, SVD_EXACT = 0, 1
 MODEL_ISING = 0
 T_PHI, T_PSI, T_SIGMA = 0, 1, 2

@@ -28,7 +28,7 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::trg::Error((code), (msg));                                   \
     } while (0)
 
-enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16X3 = 2 };
+enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16X3 = 2, P_BF16X6 = 3 };
 
 // ---- GEMM: C[b] = alpha * sum_k A[b](r,k) B[b](k,n) + beta * C[b] -----------------
 // Element (r, k) of A[b] is at A + b*sAb + r*sAr + k*sAk (likewise B, C).
@@ -41,6 +41,8 @@ struct GemmArgs {
 };
 void gemm(const GemmArgs &g, Prec prec, hipStream_t st);
 void gemm_f64(const GemmArgs &g, hipStream_t st);
+// mode 1: FP32, 2: BF16 split, 3 products; 3: BF16 split, 6 products
+void gemm_mixed(const GemmArgs &g, int mode, hipStream_t st);
 
 // ---- element-wise / layout kernels (kernels.hip) -----------------------------------
 // dst = src with axes permuted: dst dims = src dims[perm[i]].

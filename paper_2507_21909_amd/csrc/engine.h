@@ -40,15 +40,22 @@ struct DT {
     }
 };
 
+struct TimedGemm {
+    hipEvent_t a, b;
+    double flops;
+};
+
 struct Ctx {
     hipStream_t st;
     Arena *ar;
     Prec prec;
-    // optional timing of selected GEMMs
+    // HIP events around selected GEMM launches (the coarse-graining GEMMs)
     bool timing = false;
-    double ms = 0.0, flops = 0.0;
-    int launches = 0;
+    std::vector<TimedGemm> timed;
 };
+
+// gemm() bracketed by HIP events on the context's stream when c.timing is set
+void timed_gemm(Ctx &c, const GemmArgs &g, Prec prec);
 
 DT talloc(Ctx &c, std::vector<int> dims);
 DT permuted(Ctx &c, const DT &a, const std::string &la, const std::string &lt);

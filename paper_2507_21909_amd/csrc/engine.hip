@@ -197,9 +197,24 @@ DT contract(Ctx &c, const DT &a, const std::string &la, const DT &b, const std::
     return out;
 }
 
+void timed_gemm(Ctx &c, const GemmArgs &g, Prec prec) {
+    if (!c.timing) {
+        gemm(g, prec, c.st);
+        return;
+    }
+    TimedGemm t;
+    TRG_HIP_CHECK(hipEventCreate(&t.a));
+    TRG_HIP_CHECK(hipEventCreate(&t.b));
+    TRG_HIP_CHECK(hipEventRecord(t.a, c.st));
+    gemm(g, prec, c.st);
+    TRG_HIP_CHECK(hipEventRecord(t.b, c.st));
+    t.flops = 2.0 * g.M * (double)g.N * g.K * g.batch;
+    c.timed.push_back(t);
+}
+
 void gemm(const GemmArgs &g, Prec prec, hipStream_t st) {
-    (void)prec;
-    gemm_f64(g, st);
+    if (prec == P_FP64) gemm_f64(g, st);
+    else gemm_mixed(g, (int)prec, st);
 }
 
 }  // namespace trg

@@ -120,3 +120,254 @@ void gemm_f64(const GemmArgs &g, hipStream_t st) {
 }
 
 }  // namespace trg
+
+// ---------------------------------------------------------------------------
+// Mixed-precision paths for the coarse-graining contractions.
+//
+// FP32: operands rounded to FP32, v_mfma_f32_16x16x4_f32.
+// BF16xN: each operand x (rounded to FP32) is split by round-to-nearest into
+// x = x0 + x1 + x2 with x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1);
+// the product sums the split products x_i y_j with i + j <= 1 (N = 3 products)
+// or i + j <= 2 (N = 6), each on v_mfma_f32_16x16x32_bf16.
+// In both paths the FP32 MFMA accumulators are added into FP64 registers every
+// 1024 of K, so long contractions keep FP32 rounding only within a chunk.
+namespace trg {
+namespace {
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int FLUSH_K = 1024;
+
+// FP32 path: same tiling as the FP64 kernel (BK 16), LDS in FP32
+__global__ __launch_bounds__(NT) void gemm_f32_kernel(GemmArgs g) {
+    const int bz = blockIdx.z;
+    const double *A = g.A + (long)bz * g.sAb;
+    const double *B = g.B + (long)bz * g.sBb;
+    double *C = g.C + (long)bz * g.sCb;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    __shared__ float As[BK][BM + LP];
+    __shared__ float Bs[BK][BN + LP];
+    const bool a_kfast = (g.sAk == 1) || (g.sAr != 1);
+    const bool b_nfast = (g.sBn == 1) || (g.sBk != 1);
+    int ar, ak, br, bk;
+    if (a_kfast) { ar = t >> 2; ak = (t & 3) * 4; } else { ak = t >> 4; ar = (t & 15) * 4; }
+    if (b_nfast) { bk = t >> 4; br = (t & 15) * 4; } else { br = t >> 2; bk = (t & 3) * 4; }
+    float ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int r = m0 + (a_kfast ? ar : ar + i), k = k0 + (a_kfast ? ak + i : ak);
+            ra[i] = (r < g.M && k < g.K) ? (float)A[(long)r * g.sAr + (long)k * g.sAk] : 0.0f;
+            int c = n0 + (b_nfast ? br + i : br), kb = k0 + (b_nfast ? bk : bk + i);
+            rb[i] = (c < g.N && kb < g.K) ? (float)B[(long)kb * g.sBk + (long)c * g.sBn] : 0.0f;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (a_kfast) As[ak + i][ar] = ra[i]; else As[ak][ar + i] = ra[i];
+            if (b_nfast) Bs[bk][br + i] = rb[i]; else Bs[bk + i][br] = rb[i];
+        }
+    };
+    f4 acc[2][2];
+    d4 dacc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) { acc[i][j] = f4{0, 0, 0, 0}; dacc[i][j] = d4{0, 0, 0, 0}; }
+    const int nk = (g.K + BK - 1) / BK;
+    load(0);
+    store();
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            float af[2], bf[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) af[i] = As[kr][wr * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bf[j] = Bs[kr][wc * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        if (((kt + 1) * BK) % FLUSH_K == 0 || kt + 1 == nk) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) { dacc[i][j][e] += (double)acc[i][j][e]; acc[i][j][e] = 0.0f; }
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            store();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int r = m0 + wr * 32 + i * 16 + 4 * (lane >> 4) + e;
+                int c = n0 + wc * 32 + j * 16 + (lane & 15);
+                if (r < g.M && c < g.N) {
+                    double *p = C + (long)r * g.sCr + (long)c * g.sCn;
+                    double v = g.alpha * dacc[i][j][e];
+                    if (g.beta != 0.0) v += g.beta * *p;
+                    *p = v;
+                }
+            }
+}
+
+// BF16 split path: BK 32; LDS tiles row-major with k contiguous (8 bf16 per lane per MFMA)
+constexpr int BKB = 32, KP = 8;   // KP: padding in bf16 elements
+
+template <int NSPLIT, int NPROD>
+__global__ __launch_bounds__(NT) void gemm_bf16_kernel(GemmArgs g) {
+    const int bz = blockIdx.z;
+    const double *A = g.A + (long)bz * g.sAb;
+    const double *B = g.B + (long)bz * g.sBb;
+    double *C = g.C + (long)bz * g.sCb;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    __shared__ __bf16 As[NSPLIT][BM][BKB + KP];
+    __shared__ __bf16 Bs[NSPLIT][BN][BKB + KP];
+    // 64 x 32 tile = 2048 elements: 8 per thread
+    const bool a_kfast = (g.sAk == 1) || (g.sAr != 1);
+    const bool b_kfast = (g.sBk == 1) || (g.sBn != 1);
+    int ar, ak, br, bk;
+    if (a_kfast) { ar = t >> 2; ak = (t & 3) * 8; } else { ak = t >> 3; ar = (t & 7) * 8; }
+    if (b_kfast) { br = t >> 2; bk = (t & 3) * 8; } else { bk = t >> 3; br = (t & 7) * 8; }
+    float ra[8], rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            int r = m0 + (a_kfast ? ar : ar + i), k = k0 + (a_kfast ? ak + i : ak);
+            ra[i] = (r < g.M && k < g.K) ? (float)A[(long)r * g.sAr + (long)k * g.sAk] : 0.0f;
+            int c = n0 + (b_kfast ? br : br + i), kb = k0 + (b_kfast ? bk + i : bk);
+            rb[i] = (c < g.N && kb < g.K) ? (float)B[(long)kb * g.sBk + (long)c * g.sBn] : 0.0f;
+        }
+    };
+    auto split_store = [&](float x, __bf16 *dst0, long plane) {
+        __bf16 x0 = (__bf16)x;
+        float r1 = x - (float)x0;
+        __bf16 x1 = (__bf16)r1;
+        dst0[0] = x0;
+        dst0[plane] = x1;
+        if (NSPLIT > 2) {
+            float r2 = r1 - (float)x1;
+            dst0[2 * plane] = (__bf16)r2;
+        }
+    };
+    auto store = [&]() {
+        const long pa = (long)BM * (BKB + KP), pb = (long)BN * (BKB + KP);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (a_kfast) split_store(ra[i], &As[0][ar][ak + i], pa);
+            else split_store(ra[i], &As[0][ar + i][ak], pa);
+            if (b_kfast) split_store(rb[i], &Bs[0][br][bk + i], pb);
+            else split_store(rb[i], &Bs[0][br + i][bk], pb);
+        }
+    };
+    f4 acc[2][2];
+    d4 dacc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) { acc[i][j] = f4{0, 0, 0, 0}; dacc[i][j] = d4{0, 0, 0, 0}; }
+    const int nk = (g.K + BKB - 1) / BKB;
+    load(0);
+    store();
+    __syncthreads();
+    const int kq = (lane >> 4) * 8;
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) load((kt + 1) * BKB);
+        bf8 af[NSPLIT][2], bfr[NSPLIT][2];
+#pragma unroll
+        for (int s = 0; s < NSPLIT; ++s)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                af[s][i] = *reinterpret_cast<const bf8 *>(&As[s][wr * 32 + i * 16 + (lane & 15)][kq]);
+                bfr[s][i] = *reinterpret_cast<const bf8 *>(&Bs[s][wc * 32 + i * 16 + (lane & 15)][kq]);
+            }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                // smallest products first
+                if (NPROD == 6) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2 % NSPLIT][i], bfr[0][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[2 % NSPLIT][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[1][j], acc[i][j], 0, 0, 0);
+                }
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[0][j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[1][j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], acc[i][j], 0, 0, 0);
+            }
+        if (((kt + 1) * BKB) % FLUSH_K == 0 || kt + 1 == nk) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) { dacc[i][j][e] += (double)acc[i][j][e]; acc[i][j][e] = 0.0f; }
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            store();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int r = m0 + wr * 32 + i * 16 + 4 * (lane >> 4) + e;
+                int c = n0 + wc * 32 + j * 16 + (lane & 15);
+                if (r < g.M && c < g.N) {
+                    double *p = C + (long)r * g.sCr + (long)c * g.sCn;
+                    double v = g.alpha * dacc[i][j][e];
+                    if (g.beta != 0.0) v += g.beta * *p;
+                    *p = v;
+                }
+            }
+}
+
+template <typename K>
+void launch_batched(K kern, const GemmArgs &g, hipStream_t st) {
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+    for (int b0 = 0; b0 < g.batch; b0 += 65535) {
+        GemmArgs h = g;
+        h.batch = std::min(65535, g.batch - b0);
+        h.A += (long)b0 * g.sAb;
+        h.B += (long)b0 * g.sBb;
+        h.C += (long)b0 * g.sCb;
+        dim3 grid(cdiv(h.N, BN), cdiv(h.M, BM), h.batch);
+        hipLaunchKernelGGL(kern, grid, dim3(NT), 0, st, h);
+    }
+    TRG_HIP_CHECK(hipGetLastError());
+}
+}  // namespace
+
+void gemm_mixed(const GemmArgs &g, int mode, hipStream_t st) {
+    switch (mode) {
+        case 1: launch_batched(gemm_f32_kernel, g, st); break;
+        case 2: launch_batched(gemm_bf16_kernel<2, 3>, g, st); break;
+        case 3: launch_batched(gemm_bf16_kernel<3, 6>, g, st); break;
+        default: gemm_f64(g, st);
+    }
+}
+
+}  // namespace trg

@@ -131,7 +131,8 @@ struct Step {
     Step(trg_state *s) : S(s) {
         c.st = s->st;
         c.ar = &s->ar;
-        c.prec = P_FP64;
+        c.prec = (Prec)s->opt.precision;
+        c.timing = s->timing;
         kept = s->dint + 8;
     }
     int *new_kept() { return kept++; }
@@ -538,6 +539,49 @@ void triad_iso(Step &T, const DT &gram, int d1, int d2, int rcap, DT &U) {
     U.d = {d1, d2, rcap};
 }
 
+// The two big contractions of makeMG (and, with G, H, N, of makeMH), slab by
+// slab over the first leg x of E (of H), as in the paper's GPU split of
+// Table I but within one device:
+//   K1: Z[x, u, c, v, g] = sum_{a, s} EM[x, u, c, a, s] F[a, s, v, g]
+//   K2: out[x, k, l, c, g] = sum_{u, v} T23[u, v, k, l] Z[x, u, v, c, g]
+// u, v are the triad bonds (kA, kX), c the squeezed t3 bond, g the bond-swap bond.
+DT coarse_half(Step &T, const DT &em, const DT &fp, const DT &t23) {
+    Ctx &c = T.c;
+    const int X = em.d[0], U = em.d[1], C = em.d[2], Aa = em.d[3], Ss = em.d[4];
+    const int V = fp.d[2], G = fp.d[3];
+    const int Kk = t23.d[2], Ll = t23.d[3];
+    TRG_REQUIRE(fp.d[0] == Aa && fp.d[1] == Ss && t23.d[0] == U && t23.d[1] == V, -1, "coarse_half: shapes");
+    DT out = talloc(c, {X, Kk, Ll, C, G});
+    const long zslab = (long)U * C * V * G;
+    // slab group: keep one group's Z (and its permuted copy) near 1 GiB
+    int xs = (int)std::max(1L, std::min<long>(X, (long)(134217728L / std::max(1L, zslab))));
+    Arena::Mark mk = c.ar->mark();
+    DT z = talloc(c, {xs, U, C, V, G});
+    DT zp = talloc(c, {xs, U, V, C, G});
+    for (int x0 = 0; x0 < X; x0 += xs) {
+        const int nx = std::min(xs, X - x0);
+        GemmArgs g{};
+        g.M = U * C; g.N = V * G; g.K = Aa * Ss; g.batch = nx;
+        g.A = em.p + (long)x0 * U * C * Aa * Ss; g.sAr = (long)Aa * Ss; g.sAk = 1; g.sAb = (long)U * C * Aa * Ss;
+        g.B = fp.p; g.sBk = (long)V * G; g.sBn = 1; g.sBb = 0;
+        g.C = z.p; g.sCr = (long)V * G; g.sCn = 1; g.sCb = zslab;
+        g.alpha = 1.0; g.beta = 0.0;
+        timed_gemm(c, g, c.prec);
+        z.d[0] = nx;
+        zp.d[0] = nx;
+        permute(z.p, zp.p, z.d, {0, 1, 3, 2, 4}, c.st);
+        GemmArgs h{};
+        h.M = Kk * Ll; h.N = C * G; h.K = U * V; h.batch = nx;
+        h.A = t23.p; h.sAr = 1; h.sAk = (long)Kk * Ll; h.sAb = 0;
+        h.B = zp.p; h.sBk = (long)C * G; h.sBn = 1; h.sBb = zslab;
+        h.C = out.p + (long)x0 * Kk * Ll * C * G; h.sCr = (long)C * G; h.sCn = 1; h.sCb = (long)Kk * Ll * C * G;
+        h.alpha = 1.0; h.beta = 0.0;
+        timed_gemm(c, h, c.prec);
+    }
+    c.ar->release(mk);
+    return out;
+}
+
 void triad_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi) {
     trg_state *S = T.S;
     Ctx &c = T.c;
@@ -597,19 +641,19 @@ void triad_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi) {
         }
     }
     // makeMG: Phi = (E F M3)(I J M1 M2)
-    DT em = contract(c, e, "xAta", M[2], "tsc", "xAasc");
-    DT efm = contract(c, em, "xAasc", f, "aXsg", "xAXcg", c.prec);
     DT im = contract(c, UA, "ijA", M[0], "ipk", "jApk");
     DT imm = contract(c, im, "jApk", M[1], "jql", "Apkql");
-    DT ijmm = contract(c, imm, "Apkql", UX, "pqX", "AXkl");
-    phi = contract(c, efm, "xAXcg", ijmm, "AXkl", "xklcg", c.prec);
+    DT ijmm = contract(c, imm, "Apkql", UX, "pqX", "AXkl");            // T23 [kA, kX, k1, k2]
+    DT em = contract(c, e, "xAta", M[2], "tsc", "xAcas");               // [x, kA, k3, alpha, s]
+    DT fp = permuted(c, f, "aXsg", "asXg");                             // [alpha, s, kX, g]
+    phi = coarse_half(T, em, fp, ijmm);
     // makeMH: Psi = (G H N3)(K L N1 N2)
-    DT hn = contract(c, hh, "xDsb", N[2], "tsc", "xDbtc");
-    DT ghn = contract(c, g, "bYtg", hn, "xDbtc", "xYDcg", c.prec);
     DT kn = contract(c, UY, "ijY", N[0], "ipk", "jYpk");
     DT knn = contract(c, kn, "jYpk", N[1], "jql", "Ypkql");
-    DT klnn = contract(c, knn, "Ypkql", UD, "pqD", "YDkl");
-    psi = contract(c, ghn, "xYDcg", klnn, "YDkl", "xklcg", c.prec);
+    DT klnn = contract(c, knn, "Ypkql", UD, "pqD", "DYkl");            // [kD, kY, k1, k2]
+    DT hn = contract(c, hh, "xDsb", N[2], "tsc", "xDcbt");              // [x, kD, k3, beta, t]
+    DT gp = permuted(c, g, "bYtg", "btYg");                             // [beta, t, kY, g]
+    psi = coarse_half(T, hn, gp, klnn);
 }
 
 // ---------------------------------------------------------------- one step
@@ -645,6 +689,16 @@ void do_step(trg_state *S, int axis, bool triad) {
     S->sigma_last.assign(sw.sig.d[0], 0.0);
     TRG_HIP_CHECK(hipMemcpyAsync(S->sigma_last.data(), sw.sig.p, sizeof(double) * sw.sig.d[0], hipMemcpyDeviceToHost, S->st));
     TRG_HIP_CHECK(hipStreamSynchronize(S->st));
+    for (auto &t : T.c.timed) {
+        float ms = 0.0f;
+        TRG_HIP_CHECK(hipEventElapsedTime(&ms, t.a, t.b));
+        S->t_ms += ms;
+        S->t_flops += t.flops;
+        S->t_launch += 1;
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    T.c.timed.clear();
     S->k += 1;
 }
 
@@ -695,7 +749,7 @@ int trg_create(const trg_options *opt, trg_state **out) {
     *out = nullptr;
     if (!opt) return TRG_E_INVALID;
     if (opt->dim != 4 || opt->r < 1 || opt->sketch_mult < 1 || opt->power_iters < 0 ||
-        (opt->precision < 0 || opt->precision > 2) || (opt->bond_svd != 0 && opt->bond_svd != 1))
+        (opt->precision < 0 || opt->precision > 3) || (opt->bond_svd != 0 && opt->bond_svd != 1))
         return TRG_E_INVALID;
     trg_state *s = new (std::nothrow) trg_state();
     if (!s) return TRG_E_NOMEM;
@@ -934,7 +988,7 @@ extern "C" {
 
 int trg_selftest_gemm(int precision, int ta, int tb, int M, int N, int K, int batch, const double *A,
                       const double *B, double *C) {
-    if (!A || !B || !C || M < 1 || N < 1 || K < 0 || batch < 1 || precision < 0 || precision > 2)
+    if (!A || !B || !C || M < 1 || N < 1 || K < 0 || batch < 1 || precision < 0 || precision > 3)
         return TRG_E_INVALID;
     try {
         Scratch s;

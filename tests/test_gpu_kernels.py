@@ -88,3 +88,21 @@ def test_sketch_matches_oracle():
     o = sketch_omega(0x2507219090000000, 5, 3, 7, (5, 4, 3), 9)
     assert g.shape == o.shape
     assert np.max(np.abs(g - o)) < 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", [(trg.FP32, 2e-6), (trg.BF16X3, 1e-4), (trg.BF16X6, 2e-6)])
+@pytest.mark.parametrize("shape", [(1, 64, 64, 64), (2, 100, 70, 3000), (1, 33, 130, 47)])
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, True)])
+def test_gemm_mixed(prec, tol, shape, ta, tb):
+    batch, m, n, k = shape
+    _say("gemm mixed", prec, shape, ta, tb)
+    rng = np.random.default_rng(m + 3 * n + k)
+    a = rng.standard_normal((batch, k, m) if ta else (batch, m, k))
+    b = rng.standard_normal((batch, n, k) if tb else (batch, k, n))
+    c = trg.selftest_gemm(a, b, ta, tb, precision=prec)
+    aa = np.swapaxes(a, 1, 2) if ta else a
+    bb = np.swapaxes(b, 1, 2) if tb else b
+    ref = aa @ bb
+    # error relative to the natural scale of the sum, sqrt(K) for unit normals
+    err = np.max(np.abs(c - ref)) / np.sqrt(k)
+    assert err < tol, err
