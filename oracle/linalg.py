@@ -14,6 +14,12 @@
                   of every kept singular/eigen vector: column j is flipped so
                   that sum_i w(i) Q[i, j] > 0, with w a fixed irregular weight of
                   the multi-index of the row.
+* ``canonical_rotation``  the same convention for a multiplet of d nearly
+                  equal values: the columns of the multiplet are rotated to
+                  Q_m Q_z, Q_z the Q factor (diag R > 0) of Z = Q_m^T W_d with d
+                  fixed weight vectors w_0..w_{d-1}; the result depends only on
+                  the subspace the multiplet spans (for d = 1 it is the sign
+                  convention).
 
 Both Jacobi routines (their loops are in ``jacobi.c``) process the disjoint
 index pairs of a round-robin schedule simultaneously; this is the textbook
@@ -23,6 +29,7 @@ import numpy as np
 
 EPS = np.finfo(np.float64).eps
 GOLDEN = 0.6180339887498949
+SQRT2M1 = 0.41421356237309515
 RADIX = 131
 
 
@@ -166,3 +173,46 @@ def fix_signs(q, dims):
     w = sign_weights(dims)
     proj = w @ q
     return np.where(proj < 0, -1.0, 1.0)
+
+
+def basis_weights(dims, count):
+    """Weight vectors w_j(i) = 0.5 + frac(g (1 + code(i)) + j (sqrt 2 - 1)), j < count."""
+    code = np.zeros(tuple(dims), dtype=np.float64)
+    mult = 1.0
+    for ax, d in enumerate(dims):
+        shape = [1] * len(dims)
+        shape[ax] = d
+        code = code + (np.arange(d, dtype=np.float64) * mult).reshape(shape)
+        mult *= RADIX
+    x = (GOLDEN * (1.0 + code)).reshape(-1)
+    w = np.empty((x.size, count))
+    for j in range(count):
+        y = x + j * SQRT2M1
+        w[:, j] = 0.5 + (y - np.floor(y))
+    return w
+
+
+def multiplets(vals, k, tau_deg):
+    """Groups (start, size) of the first k values: neighbours closer than tau_deg * vals[0] share a group."""
+    groups = []
+    a = 0
+    for i in range(1, k + 1):
+        if i == k or (vals[i - 1] - vals[i]) > tau_deg * vals[0]:
+            groups.append((a, i - a))
+            a = i
+    return groups
+
+
+def canonical_rotation(q, vals, k, dims, tau_deg):
+    """Block-diagonal orthogonal R (k x k) that puts the first k columns of q in canonical form."""
+    rot = np.eye(k)
+    if k == 0:
+        return rot
+    groups = multiplets(vals, k, tau_deg)
+    dmax = max(d for _, d in groups)
+    w = basis_weights(dims, dmax)
+    for a, d in groups:
+        z = q[:, a:a + d].T @ w[:, :d]
+        qz, _ = qr_pos(z)
+        rot[a:a + d, a:a + d] = qz
+    return rot

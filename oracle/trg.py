@@ -37,7 +37,7 @@ import math
 
 import numpy as np
 
-from .linalg import qr_pos, jacobi_eigh, jacobi_svd, kept_count, fix_signs
+from .linalg import qr_pos, jacobi_eigh, jacobi_svd, kept_count, fix_signs, canonical_rotation
 from .philox import sketch_omega
 from .ising import ising_cp
 
@@ -53,7 +53,7 @@ class Params:
     bond_svd: str = "sketch"      # "sketch" (App. A) or "exact"
     eps_s: float = 1e-14          # singular values <= eps_s * top are zero
     eps_lam: float = 1e-14        # Gram eigenvalues <= eps_lam * top are zero
-    tau_deg: float = 1e-12        # multiplet width at a truncation cut
+    tau_deg: float = 1e-9         # multiplet width (relative to the largest value)
     eps_sq: float = 1e-14         # squeezer singular values <= eps_sq * top are dropped
 
 
@@ -81,12 +81,15 @@ def init_ising(beta, h, d=4):
 # step pieces
 # ----------------------------------------------------------------------------
 
-def resplit(phi, psi, eps_s):
+def resplit(phi, psi, eps_s, tau_deg=1e-9):
     """Exact SVD of T = Phi Psi^T through two QRs and a small SVD.
 
-    Returns (A, B, C, Dm, c) as matrices with rows = legs in natural order:
-    T / c = A B^T = C Dm^T, A and Dm isometric on the kept columns.  Columns
-    whose singular value is <= eps_s are zero in all four.
+    Returns (A, B, C, Dm, c, s) as matrices with rows = legs in natural order:
+    T / c = A B^T = C Dm^T with A and Dm isometric on the kept columns.  The
+    bond basis is canonical: within each multiplet of singular values the
+    columns of A (and Dm) are rotated by the canonical rotation R, and
+    B = Dm S', C = A S' with S' = R^T diag(s) R.  Columns whose singular value
+    is <= eps_s are zero in all four.
     """
     dims = phi.shape[:-1]
     f = int(np.prod(dims))
@@ -97,16 +100,18 @@ def resplit(phi, psi, eps_s):
     if not (c > 0 and np.isfinite(c)):
         raise FloatingPointError("re-split: non-positive or non-finite norm %r" % c)
     s = s / c
+    s = np.where(s > eps_s, s, 0.0)
+    k = int(np.count_nonzero(s))
     a = q1 @ u
     dm = q2 @ v
-    sg = fix_signs(a, dims)
-    a = a * sg
-    dm = dm * sg
-    keep = s > eps_s
-    a[:, ~keep] = 0.0
-    dm[:, ~keep] = 0.0
-    s = np.where(keep, s, 0.0)
-    return a, dm * s, a * s, dm, c, s
+    rot = np.eye(len(s))
+    rot[:k, :k] = canonical_rotation(a[:, :k], s, k, dims, tau_deg)
+    a = a @ rot
+    dm = dm @ rot
+    a[:, k:] = 0.0
+    dm[:, k:] = 0.0
+    sp = rot.T @ np.diag(s) @ rot
+    return a, dm @ sp, a @ sp, dm, c, s
 
 
 def _to_step_order(mat, dims, order):
@@ -261,9 +266,9 @@ def squeezer(kf, kb, dt, db, prm, name, logrec):
     isq = 1.0 / np.sqrt(s[:kept])
     e = rb.T @ v[:, :kept] * isq[None, :]
     f = rf.T @ u[:, :kept] * isq[None, :]
-    sg = fix_signs(e, (dt, db))
-    e = e * sg
-    f = f * sg
+    rot = canonical_rotation(e, s, kept, (dt, db), prm.tau_deg)
+    e = e @ rot
+    f = f @ rot
     eo = np.zeros((npair, prm.D))
     fo = np.zeros((npair, prm.D))
     eo[:, :kept] = e
@@ -422,7 +427,7 @@ def rg_step(state, axis, prm, method):
         raise ValueError("triad-ATRG is defined for d = 4")
     order = [axis] + [(axis + i) % d for i in range(1, d)]
     rec = dict(step=state.k, axis=axis, method=method)
-    am, bm, cm, dm, c, s = resplit(state.phi, state.psi, prm.eps_s)
+    am, bm, cm, dm, c, s = resplit(state.phi, state.psi, prm.eps_s, prm.tau_deg)
     state.logacc += 2.0 ** (-state.k) * math.log(c)
     rec["c"] = c
     rec["s"] = s.copy()

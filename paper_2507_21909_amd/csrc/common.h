@@ -19,8 +19,10 @@ struct Error : std::runtime_error {
 #define TRG_HIP_CHECK(expr)                                                              \
     do {                                                                                 \
         hipError_t _e = (expr);                                                          \
-        if (_e != hipSuccess)                                                            \
+        if (_e != hipSuccess) {                                                          \
+            (void)hipGetLastError();                                                     \
             throw ::trg::Error(-5, std::string(#expr) + ": " + hipGetErrorString(_e));   \
+        }                                                                                \
     } while (0)
 
 #define TRG_REQUIRE(cond, code, msg)                                                     \
@@ -65,6 +67,14 @@ void zero_tail_cols(double *a, long rows, int cols, long ld, const int *kept_dev
 // `dims` (row-major over the GPU layout), each leg contributing idx * pw[leg].
 void sign_vector(const double *q, long rows, int cols, long ld, const std::vector<int> &dims,
                  const std::vector<double> &pw, double *sg, hipStream_t st);
+// Canonical basis within multiplets: rot (cols x cols, block diagonal) such that
+// q rot has, in every group of the first *k_dev values closer than tau * vals[0],
+// the columns Q_m Q_z with Q_z the Q factor of Q_m^T W (fixed weights w_l of the
+// row multi-index).  z_work holds cols * 16 doubles; status gets 2 if a group
+// is larger than 16.
+void canonical_rotation(const double *q, long rows, int cols, long ld, const std::vector<int> &dims,
+                        const std::vector<double> &pw, const double *vals, const int *k_dev, double tau,
+                        double *z_work, double *rot, int *status, hipStream_t st);
 // a[:, j] *= sg[j]
 void scale_cols(double *a, long rows, int cols, long ld, const double *sg, hipStream_t st);
 

@@ -86,14 +86,15 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
             __syncthreads();
         }
     }
-    // epilogue: lane holds D[4*(lane/16)+i][lane%16] of each 16x16 tile
+    // epilogue: item e of lane l holds D[l/16 + 4e][l%16] of each 16x16 tile
+    // (the f64 16x16x4 output layout, checked against a host GEMM)
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                int r = m0 + wr * 32 + i * 16 + 4 * (lane >> 4) + e;
+                int r = m0 + wr * 32 + i * 16 + (lane >> 4) + 4 * e;
                 int c = n0 + wc * 32 + j * 16 + (lane & 15);
                 if (r < g.M && c < g.N) {
                     double *p = C + (long)r * g.sCr + (long)c * g.sCn;
@@ -129,14 +130,15 @@ void gemm_f64(const GemmArgs &g, hipStream_t st) {
 // x = x0 + x1 + x2 with x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1);
 // the product sums the split products x_i y_j with i + j <= 1 (N = 3 products)
 // or i + j <= 2 (N = 6), each on v_mfma_f32_16x16x32_bf16.
-// In both paths the FP32 MFMA accumulators are added into FP64 registers every
-// 1024 of K, so long contractions keep FP32 rounding only within a chunk.
+// In both paths the FP32 MFMA accumulators are added into FP64 registers after
+// every K tile, so FP32 rounding stays within partial sums of 16 (FP32) or 32
+// (BF16) terms however long the contraction.
 namespace trg {
 namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int FLUSH_K = 1024;
+constexpr int FLUSH_K = 16;   // FP32 partial sums span one K tile at most
 
 // FP32 path: same tiling as the FP64 kernel (BK 16), LDS in FP32
 __global__ __launch_bounds__(NT) void gemm_f32_kernel(GemmArgs g) {

@@ -175,6 +175,78 @@ __global__ void sketch_kernel(double *out, SketchArgs a) {
     }
 }
 
+// Z[j][l] = sum_i Q[i, j] w_l(i), w_l(i) = 0.5 + frac(g (1 + code(i)) + l (sqrt 2 - 1)), l < L
+__global__ void weights_dot_kernel(const double *q, long rows, int cols, long ld, SignArgs a, int L, double *z) {
+    const double golden = 0.6180339887498949, c2 = 0.41421356237309515;
+    int j = blockIdx.x;
+    double acc[16];
+    for (int l = 0; l < 16; ++l) acc[l] = 0.0;
+    for (long r = threadIdx.x; r < rows; r += blockDim.x) {
+        long rem = r;
+        double code = 0.0;
+        for (int d = a.nd - 1; d >= 0; --d) {
+            long qd = rem / a.dd[d];
+            code += (double)(rem - qd * a.dd[d]) * a.pw[d];
+            rem = qd;
+        }
+        double x = golden * (1.0 + code);
+        double v = q[r * ld + j];
+        for (int l = 0; l < L; ++l) {
+            double y = x + l * c2;
+            acc[l] += (0.5 + (y - floor(y))) * v;
+        }
+    }
+    __shared__ double red[256];
+    for (int l = 0; l < L; ++l) {
+        red[threadIdx.x] = acc[l];
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) z[(long)j * L + l] = red[0];
+        __syncthreads();
+    }
+}
+
+// Block-diagonal canonical rotation (n x n): identity, except on each multiplet
+// [a, a+d) of the first k values (neighbours within tau * v[0]) where it is the
+// Q factor (positive diagonal R) of Z_m[r][c] = z[(a+r)*L + c], c < d.
+__global__ void canon_rot_kernel(const double *v, int n, const int *kdev, double tau, const double *z, int L,
+                                 double *rot, int *status) {
+    if (threadIdx.x || blockIdx.x) return;
+    int k = *kdev;
+    for (long i = 0; i < (long)n * n; ++i) rot[i] = (i / n == i % n) ? 1.0 : 0.0;
+    if (k <= 0) return;
+    int a = 0;
+    for (int i = 1; i <= k; ++i) {
+        if (i < k && (v[i - 1] - v[i]) <= tau * v[0]) continue;
+        int d = i - a;
+        if (d > L) {
+            *status = 2;
+        } else {
+            double qm[16][16];
+            for (int c = 0; c < d; ++c) {
+                double col[16];
+                for (int r = 0; r < d; ++r) col[r] = z[(long)(a + r) * L + c];
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int p = 0; p < c; ++p) {
+                        double dot = 0.0;
+                        for (int r = 0; r < d; ++r) dot += qm[r][p] * col[r];
+                        for (int r = 0; r < d; ++r) col[r] -= dot * qm[r][p];
+                    }
+                double nrm = 0.0;
+                for (int r = 0; r < d; ++r) nrm += col[r] * col[r];
+                nrm = sqrt(nrm);
+                for (int r = 0; r < d; ++r) qm[r][c] = nrm > 0.0 ? col[r] / nrm : (r == c ? 1.0 : 0.0);
+            }
+            for (int r = 0; r < d; ++r)
+                for (int c = 0; c < d; ++c) rot[(long)(a + r) * n + (a + c)] = qm[r][c];
+        }
+        a = i;
+    }
+}
+
 inline unsigned grid_for(long n) { return (unsigned)std::min<long>((n + 255) / 256, 65536L); }
 }  // namespace
 
@@ -307,4 +379,22 @@ void philox_sketch(double *out, uint64_t seed, int step, uint32_t instance, cons
     TRG_HIP_CHECK(hipGetLastError());
 }
 
+}  // namespace trg
+
+namespace trg {
+void canonical_rotation(const double *q, long rows, int cols, long ld, const std::vector<int> &dims,
+                        const std::vector<double> &pw, const double *vals, const int *k_dev, double tau,
+                        double *z_work, double *rot, int *status, hipStream_t st) {
+    SignArgs a{};
+    a.nd = (int)dims.size();
+    TRG_REQUIRE(a.nd <= MAXD && pw.size() == dims.size(), -1, "canonical_rotation: bad dims");
+    long prod = 1;
+    for (int i = 0; i < a.nd; ++i) { a.dd[i] = dims[i]; a.pw[i] = pw[i]; prod *= dims[i]; }
+    TRG_REQUIRE(prod == rows, -1, "canonical_rotation: dims do not match rows");
+    if (cols == 0) return;
+    const int L = 16;
+    hipLaunchKernelGGL(weights_dot_kernel, dim3(cols), dim3(256), 0, st, q, rows, cols, ld, a, L, z_work);
+    hipLaunchKernelGGL(canon_rot_kernel, dim3(1), dim3(64), 0, st, vals, cols, k_dev, tau, z_work, L, rot, status);
+    TRG_HIP_CHECK(hipGetLastError());
+}
 }  // namespace trg

@@ -38,7 +38,7 @@ struct trg_state {
 namespace trg {
 namespace {
 
-constexpr double EPS_S = 1e-14, EPS_LAM = 1e-14, EPS_SQ = 1e-14, TAU_DEG = 1e-12;
+constexpr double EPS_S = 1e-14, EPS_LAM = 1e-14, EPS_SQ = 1e-14, TAU_DEG = 1e-9;
 
 // ---------------------------------------------------------------- small kernels
 __global__ void resplit_norm_kernel(double *s, int n, int k, double *logacc, double eps, int *status) {
@@ -53,6 +53,16 @@ __global__ void resplit_norm_kernel(double *s, int n, int k, double *logacc, dou
         double v = s[i] / c;
         s[i] = v > eps ? v : 0.0;
     }
+}
+
+// S' = R^T diag(s) R (n x n)
+__global__ void sprime_kernel(const double *rot, const double *s, int n, double *sp) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * n) return;
+    int r = i / n, c = i % n;
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc += rot[(long)k * n + r] * s[k] * rot[(long)k * n + c];
+    sp[i] = acc;
 }
 
 __global__ void mask_sign_kernel(double *sg, const double *s, int n) {
@@ -203,30 +213,38 @@ Split resplit(Step &T, const std::vector<int> &order) {
     hipLaunchKernelGGL(resplit_norm_kernel, dim3(1), dim3(1), 0, c.st, s.p, chi, S->k, S->dscal, EPS_S, S->dint);
     DT A = contract(c, q1, "Fa", u, "ab", "Fb");
     DT Dm = contract(c, q2, "Fa", v, "ab", "Fb");
-    double *sg = c.ar->dalloc(chi);
+    // canonical bond basis: rotation within multiplets of s, B = Dm S', C = A S'
+    int *kpos = T.new_kept();
+    kept_count(s.p, chi, chi, 0.0, -1.0, kpos, c.st);           // number of s > 0
     std::vector<int> nd(S->dims.begin(), S->dims.end());
-    sign_vector(A.p, F, chi, chi, nd, pow131(d), sg, c.st);
-    hipLaunchKernelGGL(mask_sign_kernel, dim3(1), dim3(64), 0, c.st, sg, s.p, chi);
-    scale_cols(A.p, F, chi, chi, sg, c.st);
-    scale_cols(Dm.p, F, chi, chi, sg, c.st);
+    DT rot = talloc(c, {chi, chi});
+    double *zw = c.ar->dalloc((size_t)chi * 16);
+    canonical_rotation(A.p, F, chi, chi, nd, pow131(d), s.p, kpos, TAU_DEG, zw, rot.p, S->dint, c.st);
+    DT A2 = contract(c, A, "Fa", rot, "ab", "Fb");
+    DT D2 = contract(c, Dm, "Fa", rot, "ab", "Fb");
+    zero_tail_cols(A2.p, F, chi, chi, kpos, c.st);
+    zero_tail_cols(D2.p, F, chi, chi, kpos, c.st);
+    DT sp = talloc(c, {chi, chi});
+    hipLaunchKernelGGL(sprime_kernel, dim3(g1((long)chi * chi)), dim3(256), 0, c.st, rot.p, s.p, chi, sp.p);
+    DT B2 = contract(c, D2, "Fa", sp, "ab", "Fb");
+    DT C2 = contract(c, A2, "Fa", sp, "ab", "Fb");
     // tensors in step order
     std::string nat, stp;
     for (int i = 0; i < d; ++i) nat += (char)('a' + i);
     for (int i = 0; i < d; ++i) stp += (char)('a' + order[i]);
     nat += 'z';
     stp += 'z';
-    A.d = nd;
-    A.d.push_back(chi);
-    Dm.d = A.d;
+    std::vector<int> fd = nd;
+    fd.push_back(chi);
+    A2.d = fd;
+    D2.d = fd;
+    B2.d = fd;
+    C2.d = fd;
     Split o;
-    o.A = permuted(c, A, nat, stp);
-    o.Dm = permuted(c, Dm, nat, stp);
-    o.B = talloc(c, o.Dm.d);
-    copy(o.B.p, o.Dm.p, o.Dm.n(), c.st);
-    scale_axis(o.B.p, o.B.d, d, s.p, 1, c.st);
-    o.C = talloc(c, o.A.d);
-    copy(o.C.p, o.A.p, o.A.n(), c.st);
-    scale_axis(o.C.p, o.C.d, d, s.p, 1, c.st);
+    o.A = permuted(c, A2, nat, stp);
+    o.Dm = permuted(c, D2, nat, stp);
+    o.B = permuted(c, B2, nat, stp);
+    o.C = permuted(c, C2, nat, stp);
     o.s = s;
     return o;
 }
@@ -301,6 +319,8 @@ Swap bond_swap(Step &T, const Split &sp) {
     // ---- randomized SVD of M applied directly (App. A, eq. bond1 / bond2)
     DT Bp = permuted(c, Bt, "x" + tl + "a", tl + "xa");   // [j, x, alpha]
     DT Cp = permuted(c, Ct, "x" + tl + "b", tl + "xb");   // [i, x, beta]
+    Bp.d = {(int)J, x, chi};
+    Cp.d = {(int)I, x, chi};
     DT om = talloc(c, {(int)J, chi, m});
     philox_sketch(om.p, S->opt.seed, S->k, S->opt.instance, td, chi, m, 1, c.st);
     DT Q = talloc(c, {(int)(I * chi), m}), Qp = talloc(c, {(int)(J * chi), m}), Rp = talloc(c, {m, m}), Rq = talloc(c, {m, m});
@@ -414,62 +434,103 @@ void env_grams(Step &T, const DT &tf, const DT &bf, const DT &penv, const DT &tb
     kb.d = {dt * db, dt * db};
 }
 
-// projector pair [dt, db, D]: E (forward) and F (backward)
-void squeezer(Step &T, const DT &kf, const DT &kb, int dt, int db, DT &E, DT &F) {
+// Projector pairs for `cnt` squeezers with the same pair dims (dt, db):
+// kf, kb hold cnt matrices each (n x n, n = dt*db); E[i], F[i] are [dt, db, D].
+void squeezers(Step &T, const double *kf, const double *kb, int cnt, int dt, int db, DT *E, DT *F) {
     trg_state *S = T.S;
     Ctx &c = T.c;
     const int n = dt * db, D = S->D;
-    // eigen-decompositions of K_f and K_b in one batch
-    double *kk = c.ar->dalloc((size_t)2 * n * n);
-    copy(kk, kf.p, (size_t)n * n, c.st);
-    copy(kk + (size_t)n * n, kb.p, (size_t)n * n, c.st);
-    DT lam = talloc(c, {2, n}), vec = talloc(c, {2, n, n});
-    eig_psd(T, kk, 2, n, lam.p, vec.p);
-    DT sq = talloc(c, {2, n});
-    hipLaunchKernelGGL(sqrt_clamp_kernel, dim3(g1(n)), dim3(256), 0, c.st, lam.p, sq.p, n, EPS_LAM);
-    hipLaunchKernelGGL(sqrt_clamp_kernel, dim3(g1(n)), dim3(256), 0, c.st, lam.p + n, sq.p + n, n, EPS_LAM);
-    DT wf{vec.p, {n, n}}, wb{vec.p + (size_t)n * n, {n, n}};
-    // R_f R_b^T = diag(sqf) Wf^T Wb diag(sqb)
-    DT g = contract(c, wf, "pi", wb, "pj", "ij");
-    scale_axis(g.p, g.d, 0, sq.p, 1, c.st);
-    scale_axis(g.p, g.d, 1, sq.p + n, 1, c.st);
-    DT s = talloc(c, {n}), u = talloc(c, {n, n}), v = talloc(c, {n, n});
-    svd_rowmajor(T, g, s.p, u.p, v.p);
-    int *kept = T.new_kept();
-    kept_count(s.p, n, D, EPS_SQ, TAU_DEG, kept, c.st);
-    DT is = talloc(c, {n});
-    hipLaunchKernelGGL(isqrt_kept_kernel, dim3(g1(n)), dim3(256), 0, c.st, s.p, is.p, n, kept);
-    // E = Wb diag(sqb) V[:, :D] S^-1/2 ; F = Wf diag(sqf) U[:, :D] S^-1/2
-    DT vd = talloc(c, {n, D}), ud = talloc(c, {n, D});
-    {
+    const size_t nn = (size_t)n * n;
+    // eigen-decompositions of all K_f, K_b in one batch: [f0, b0, f1, b1, ...]
+    double *kk = c.ar->dalloc(2 * cnt * nn);
+    for (int i = 0; i < cnt; ++i) {
+        copy(kk + (2 * i) * nn, kf + i * nn, nn, c.st);
+        copy(kk + (2 * i + 1) * nn, kb + i * nn, nn, c.st);
+    }
+    DT lam = talloc(c, {2 * cnt, n}), vec = talloc(c, {2 * cnt, n, n}), sq = talloc(c, {2 * cnt, n});
+    eig_psd(T, kk, 2 * cnt, n, lam.p, vec.p);
+    for (int i = 0; i < 2 * cnt; ++i)
+        hipLaunchKernelGGL(sqrt_clamp_kernel, dim3(g1(n)), dim3(256), 0, c.st, lam.p + (size_t)i * n, sq.p + (size_t)i * n,
+                           n, EPS_LAM);
+    // R_f R_b^T = diag(sqf) Wf^T Wb diag(sqb), all cnt in one batch
+    DT gm = talloc(c, {cnt, n, n});
+    for (int i = 0; i < cnt; ++i) {
+        GemmArgs ga{};
+        ga.M = n; ga.N = n; ga.K = n; ga.batch = 1;
+        ga.A = vec.p + (2 * i) * nn; ga.sAr = 1; ga.sAk = n;           // Wf^T
+        ga.B = vec.p + (2 * i + 1) * nn; ga.sBk = n; ga.sBn = 1;       // Wb
+        ga.C = gm.p + i * nn; ga.sCr = n; ga.sCn = 1;
+        ga.alpha = 1.0;
+        gemm(ga, P_FP64, c.st);
+        DT gi{gm.p + i * nn, {n, n}};
+        scale_axis(gi.p, gi.d, 0, sq.p + (size_t)(2 * i) * n, 1, c.st);
+        scale_axis(gi.p, gi.d, 1, sq.p + (size_t)(2 * i + 1) * n, 1, c.st);
+    }
+    // SVDs (Jacobi wants column-major: transpose each)
+    DT gt = talloc(c, {cnt, n, n});
+    permute(gm.p, gt.p, {cnt, n, n}, {0, 2, 1}, c.st);
+    DT s = talloc(c, {cnt, n}), u = talloc(c, {cnt, n, n}), v = talloc(c, {cnt, n, n});
+    svd_colmajor(T, gt.p, cnt, n, n, s.p, u.p, v.p);
+    for (int i = 0; i < cnt; ++i) {
+        int *kept = T.new_kept();
+        const double *si = s.p + (size_t)i * n;
+        kept_count(si, n, D, EPS_SQ, TAU_DEG, kept, c.st);
+        DT is = talloc(c, {n});
+        hipLaunchKernelGGL(isqrt_kept_kernel, dim3(g1(n)), dim3(256), 0, c.st, si, is.p, n, kept);
+        // E = Wb diag(sqb) V[:, :D] S^-1/2 ; F = Wf diag(sqf) U[:, :D] S^-1/2
+        DT vd = talloc(c, {n, D}), ud = talloc(c, {n, D});
+        DT vs = talloc(c, {n, n}), us = talloc(c, {n, n});
+        copy(vs.p, v.p + i * nn, nn, c.st);
+        scale_axis(vs.p, vs.d, 0, sq.p + (size_t)(2 * i + 1) * n, 1, c.st);
+        copy(us.p, u.p + i * nn, nn, c.st);
+        scale_axis(us.p, us.d, 0, sq.p + (size_t)(2 * i) * n, 1, c.st);
         GemmArgs ga{};
         ga.M = n; ga.N = D; ga.K = n; ga.batch = 1;
-        ga.A = wb.p; ga.sAr = n; ga.sAk = 1;
-        ga.B = v.p; ga.sBk = n; ga.sBn = 1;
+        ga.A = vec.p + (2 * i + 1) * nn; ga.sAr = n; ga.sAk = 1;
+        ga.B = vs.p; ga.sBk = n; ga.sBn = 1;
         ga.C = vd.p; ga.sCr = D; ga.sCn = 1;
         ga.alpha = 1.0;
-        // scale rows of V by sqb first: V' = diag(sqb) V
-        DT vs = talloc(c, {n, n});
-        copy(vs.p, v.p, (size_t)n * n, c.st);
-        scale_axis(vs.p, vs.d, 0, sq.p + n, 1, c.st);
-        ga.B = vs.p;
         gemm(ga, P_FP64, c.st);
-        DT us = talloc(c, {n, n});
-        copy(us.p, u.p, (size_t)n * n, c.st);
-        scale_axis(us.p, us.d, 0, sq.p, 1, c.st);
-        ga.A = wf.p; ga.B = us.p; ga.C = ud.p;
+        ga.A = vec.p + (2 * i) * nn; ga.B = us.p; ga.C = ud.p;
         gemm(ga, P_FP64, c.st);
+        scale_axis(vd.p, vd.d, 1, is.p, 1, c.st);
+        scale_axis(ud.p, ud.d, 1, is.p, 1, c.st);
+        // canonical basis of the new leg within multiplets of S
+        DT rot = talloc(c, {D, D});
+        double *zw = c.ar->dalloc((size_t)D * 16);
+        canonical_rotation(vd.p, n, D, D, {dt, db}, {1.0, 131.0}, si, kept, TAU_DEG, zw, rot.p, S->dint, c.st);
+        E[i] = contract(c, vd, "pk", rot, "kl", "pl");
+        E[i].d = {dt, db, D};
+        F[i] = contract(c, ud, "pk", rot, "kl", "pl");
+        F[i].d = {dt, db, D};
     }
-    scale_axis(vd.p, vd.d, 1, is.p, 1, c.st);
-    scale_axis(ud.p, ud.d, 1, is.p, 1, c.st);
-    double *sg = c.ar->dalloc(D);
-    sign_vector(vd.p, n, D, D, {dt, db}, {1.0, 131.0}, sg, c.st);
-    scale_cols(vd.p, n, D, D, sg, c.st);
-    scale_cols(ud.p, n, D, D, sg, c.st);
-    E = vd;
-    E.d = {dt, db, D};
-    F = ud;
-    F.d = {dt, db, D};
+}
+
+// squeezers of the transverse positions `pos` (all non-identity), batched by pair dims
+void squeezer_set(Step &T, const std::vector<int> &pos, const std::vector<int> &pd, const DT *kf, const DT *kb,
+                  DT *E, DT *F) {
+    Ctx &c = T.c;
+    std::vector<bool> done(pos.size(), false);
+    for (size_t i = 0; i < pos.size(); ++i) {
+        if (done[i]) continue;
+        std::vector<size_t> grp;
+        for (size_t j = i; j < pos.size(); ++j)
+            if (!done[j] && pd[j] == pd[i]) grp.push_back(j);
+        const int n = pd[i] * pd[i];
+        const size_t nn = (size_t)n * n;
+        double *f = c.ar->dalloc(grp.size() * nn), *b = c.ar->dalloc(grp.size() * nn);
+        for (size_t g = 0; g < grp.size(); ++g) {
+            copy(f + g * nn, kf[grp[g]].p, nn, c.st);
+            copy(b + g * nn, kb[grp[g]].p, nn, c.st);
+        }
+        std::vector<DT> e(grp.size()), ff(grp.size());
+        squeezers(T, f, b, (int)grp.size(), pd[i], pd[i], e.data(), ff.data());
+        for (size_t g = 0; g < grp.size(); ++g) {
+            E[pos[grp[g]]] = e[g];
+            F[pos[grp[g]]] = ff[g];
+            done[grp[g]] = true;
+        }
+    }
 }
 
 void identity_squeezer(Step &T, int dt, int db, DT &E, DT &F) {
@@ -495,17 +556,19 @@ void atrg_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi) {
     DT oe = talloc(c, {ng, ng});
     copy(oe.p, pe.p, (size_t)ng * ng, c.st);
     scale_axis(oe.p, oe.d, 0, s2.p, 1, c.st);
-    DT E[3], F[3];
+    DT E[3], F[3], KF[3], KB[3];
+    std::vector<int> pos_sq, pd_sq;
     for (int pos = 0; pos < 3; ++pos) {
-        int dt = A.d[pos + 1], db = sw.X.d[pos + 1];
-        if (dt * db <= D) {
-            identity_squeezer(T, dt, db, E[pos], F[pos]);
+        int dd = A.d[pos + 1];
+        if (dd * dd <= D) {
+            identity_squeezer(T, dd, dd, E[pos], F[pos]);
         } else {
-            DT kf, kb;
-            env_grams(T, A, Xs, pe, sw.Y, Dm, oe, pos, kf, kb);
-            squeezer(T, kf, kb, dt, db, E[pos], F[pos]);
+            env_grams(T, A, Xs, pe, sw.Y, Dm, oe, pos, KF[pos_sq.size()], KB[pos_sq.size()]);
+            pos_sq.push_back(pos);
+            pd_sq.push_back(dd);
         }
     }
+    squeezer_set(T, pos_sq, pd_sq, KF, KB, E, F);
     // makeG: G[x, k1, k2, k3, g] = A X sigma E1 E2 E3 (pairwise, as in the oracle)
     DT t = contract(c, A, "xijka", E[0], "iIp", "xjkaIp");
     t = contract(c, t, "xjkaIp", Xs, "aIJKg", "xjkpJKg");
@@ -518,25 +581,33 @@ void atrg_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi) {
 }
 
 // ---------------------------------------------------------------- triad-ATRG
-void triad_iso(Step &T, const DT &gram, int d1, int d2, int rcap, DT &U) {
+// triad isometries U[(t1, t2), k] of the four pair Grams (eq. HOSVD), one batch
+void triad_isos(Step &T, const DT *grams, int d1, int d2, int rcap, DT *U) {
     Ctx &c = T.c;
     const int n = d1 * d2;
+    const size_t nn = (size_t)n * n;
     if (n <= rcap) {
-        U = talloc(c, {d1, d2, n});
-        hipLaunchKernelGGL(eye_kernel, dim3(g1((long)n * n)), dim3(256), 0, c.st, U.p, n);
+        for (int i = 0; i < 4; ++i) {
+            U[i] = talloc(c, {d1, d2, n});
+            hipLaunchKernelGGL(eye_kernel, dim3(g1((long)nn)), dim3(256), 0, c.st, U[i].p, n);
+        }
         return;
     }
-    DT lam = talloc(c, {n}), vec = talloc(c, {n, n});
-    eig_psd(T, gram.p, 1, n, lam.p, vec.p);
-    int *kept = T.new_kept();
-    kept_count(lam.p, n, rcap, EPS_LAM, TAU_DEG, kept, c.st);
-    U = talloc(c, {n, rcap});
-    col_slice(c, vec.p, n, n, rcap, U.p);
-    zero_tail_cols(U.p, n, rcap, rcap, kept, c.st);
-    double *sg = c.ar->dalloc(rcap);
-    sign_vector(U.p, n, rcap, rcap, {d1, d2}, {1.0, 131.0}, sg, c.st);
-    scale_cols(U.p, n, rcap, rcap, sg, c.st);
-    U.d = {d1, d2, rcap};
+    double *kk = c.ar->dalloc(4 * nn);
+    for (int i = 0; i < 4; ++i) copy(kk + i * nn, grams[i].p, nn, c.st);
+    DT lam = talloc(c, {4, n}), vec = talloc(c, {4, n, n});
+    eig_psd(T, kk, 4, n, lam.p, vec.p);
+    for (int i = 0; i < 4; ++i) {
+        int *kept = T.new_kept();
+        kept_count(lam.p + (size_t)i * n, n, rcap, EPS_LAM, TAU_DEG, kept, c.st);
+        U[i] = talloc(c, {n, rcap});
+        col_slice(c, vec.p + i * nn, n, n, rcap, U[i].p);
+        zero_tail_cols(U[i].p, n, rcap, rcap, kept, c.st);
+        double *sg = c.ar->dalloc(rcap);
+        sign_vector(U[i].p, n, rcap, rcap, {d1, d2}, {1.0, 131.0}, sg, c.st);
+        scale_cols(U[i].p, n, rcap, rcap, sg, c.st);
+        U[i].d = {d1, d2, rcap};
+    }
 }
 
 // The two big contractions of makeMG (and, with G, H, N, of makeMH), slab by
@@ -606,11 +677,10 @@ void triad_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi) {
     DT gy = contract(c, Ys2, "aijtg", Y, "akltg", "ijkl");
     DT dy = contract(c, Dm, "xijta", ysy, "ab", "xijtb");
     DT gd = contract(c, dy, "xijtb", Dm, "xkltb", "ijkl");
-    DT UA, UX, UY, UD;
-    triad_iso(T, ga, d1, d2, rcap, UA);
-    triad_iso(T, gx, d1, d2, rcap, UX);
-    triad_iso(T, gy, d1, d2, rcap, UY);
-    triad_iso(T, gd, d1, d2, rcap, UD);
+    DT grams[4] = {ga, gx, gy, gd}, Us[4];
+    for (auto &gg : grams) gg.d = {d1 * d2, d1 * d2};
+    triad_isos(T, grams, d1, d2, rcap, Us);
+    DT &UA = Us[0], &UX = Us[1], &UY = Us[2], &UD = Us[3];
     // triad tensors
     DT e = contract(c, A, "xijta", UA, "ijk", "xkta");
     DT f = contract(c, X, "aijtg", UX, "ijk", "aktg");
@@ -629,17 +699,19 @@ void triad_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi) {
     DT xt = contract(c, f, "aktg", UX, "ijk", "aijtg");
     DT yt = contract(c, g, "bktg", UY, "ijk", "bijtg");
     DT dt = contract(c, hh, "xktb", UD, "ijk", "xijtb");
-    DT M[3], N[3];
+    DT M[3], N[3], KF[3], KB[3];
     const int dd[3] = {d1, d2, d3};
+    std::vector<int> pos_sq, pd_sq;
     for (int pos = 0; pos < 3; ++pos) {
         if (dd[pos] * dd[pos] <= D) {
             identity_squeezer(T, dd[pos], dd[pos], M[pos], N[pos]);
         } else {
-            DT kf, kb;
-            env_grams(T, at, xt, p, yt, dt, o, pos, kf, kb);
-            squeezer(T, kf, kb, dd[pos], dd[pos], M[pos], N[pos]);
+            env_grams(T, at, xt, p, yt, dt, o, pos, KF[pos_sq.size()], KB[pos_sq.size()]);
+            pos_sq.push_back(pos);
+            pd_sq.push_back(dd[pos]);
         }
     }
+    squeezer_set(T, pos_sq, pd_sq, KF, KB, M, N);
     // makeMG: Phi = (E F M3)(I J M1 M2)
     DT im = contract(c, UA, "ijA", M[0], "ipk", "jApk");
     DT imm = contract(c, im, "jApk", M[1], "jql", "Apkql");

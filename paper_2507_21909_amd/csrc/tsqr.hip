@@ -17,11 +17,28 @@ namespace trg {
 namespace {
 constexpr int NT = 256;
 
+// LDS per workgroup available to one kernel (queried once; 64 KiB if unknown)
+size_t lds_limit() {
+    static size_t lim = 0;
+    if (!lim) {
+        int dev = 0, v = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+            (void)hipGetLastError();
+            v = 65536;
+        }
+        lim = (size_t)v;
+    }
+    return lim;
+}
+
+inline size_t lds_bytes(int br, int n) { return ((size_t)br * n + 64 + 8 + 256) * sizeof(double) + 64 * sizeof(double); }
+
+// rows per block: the largest of 1024, 512, 256, 128, 64 (and >= n) whose tile fits in LDS
 inline int block_rows(int n) {
-    int br = 256;
-    if (n <= 16) br = 1024;
-    else if (n <= 32) br = 512;
-    return br;
+    for (int br : {1024, 512, 256, 128, 64})
+        if (br >= n && lds_bytes(br, n) <= lds_limit() && (size_t)br * n <= 16384) return br;
+    return 64;
 }
 
 __device__ double block_sum(double v, double *red) {
@@ -161,11 +178,13 @@ void tsqr(const double *a, long m, int n, double *q, double *r, double *ws, hipS
     TRG_REQUIRE(m >= n, -6, "tsqr: needs m >= n");
     const int BR = block_rows(n);
     const size_t lds = ((size_t)BR * n + 64 + 8 + 256) * sizeof(double);
-    static bool attr_set = false;
-    if (!attr_set) {
-        TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(qr_block_kernel),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attr_set = true;
+    TRG_REQUIRE(lds_bytes(BR, n) <= lds_limit(), -6, "tsqr: LDS tile does not fit");
+    static size_t attr_set = 0;
+    if (lds > 65536 && lds > attr_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(qr_block_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            (void)hipGetLastError();
+        attr_set = lds;
     }
     std::vector<Level> lv;
     double *p = ws;

@@ -90,3 +90,33 @@ def test_error_codes():
     with pytest.raises(trg.TrgError) as e:
         s.tensor_init(trg.MODEL_ISING, -0.1, 0.0, 4)
     assert e.value.code == -1
+
+
+def _golden(name):
+    import json
+    import os
+    p = os.path.join(os.path.dirname(__file__), "golden", name + ".json")
+    if not os.path.exists(p):
+        pytest.skip("golden values %s not generated (tests/golden/make_golden.py)" % name)
+    return json.load(open(p))
+
+
+@pytest.mark.parametrize("name", ["triad_d16_l1024", "triad_d16_h1e-4_16steps", "triad_d32_12steps"])
+def test_triad_against_stored_oracle_values(name):
+    """Full-size parity: the FP64 GPU path vs oracle values stored by make_golden.py."""
+    g = _golden(name)
+    c = g["params"]
+    n = len(g["log_z"])
+    if n < c["nsteps"]:
+        pytest.skip("golden file %s incomplete (%d of %d steps)" % (name, n, c["nsteps"]))
+    _say("golden", name)
+    s = trg.Solver(seed=c["seed"])
+    s.tensor_init(trg.MODEL_ISING, c["beta"], c["h"], c["D"])
+    worst = 0.0
+    for i in range(n):
+        s.triad_atrg_step(i % 4)
+        f = s.log_z_per_site()
+        rel = abs(f - g["log_z"][i]) / abs(g["log_z"][i])
+        worst = max(worst, rel)
+        _say("  step %2d  gpu %.16f  oracle %.16f  rel %.2e" % (i, f, g["log_z"][i], rel))
+    assert worst <= TOL

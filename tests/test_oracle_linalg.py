@@ -108,3 +108,44 @@ def test_sign_weights_do_not_depend_on_padding():
     assert abs(float(sign_weights((4, 4)) @ anti[:, 0])) > 1e-3
     sg = fix_signs(np.hstack([anti, -anti]), (4, 4))
     assert sg[0] == -sg[1]
+
+
+def test_canonical_rotation_depends_only_on_the_subspace():
+    from oracle.linalg import canonical_rotation
+    rng = np.random.default_rng(21)
+    dims = (3, 4, 2)
+    n = 24
+    q, _ = np.linalg.qr(rng.standard_normal((n, 6)))
+    vals = np.array([1.0, 0.5, 0.5, 0.5, 0.2, 0.1])
+    rot = canonical_rotation(q, vals, 6, dims, 1e-9)
+    c1 = q @ rot
+    # rotate the 3-fold multiplet (and flip a singlet): same canonical basis
+    r3, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    q2 = q.copy()
+    q2[:, 1:4] = q[:, 1:4] @ r3
+    q2[:, 4] *= -1
+    c2 = q2 @ canonical_rotation(q2, vals, 6, dims, 1e-9)
+    assert np.max(np.abs(c1 - c2)) < 1e-13
+    # singlets: the sign convention
+    single = canonical_rotation(q, np.array([6, 5, 4, 3, 2, 1.0]), 6, dims, 1e-9)
+    assert np.allclose(single, np.diag(fix_signs(q, dims)))
+
+
+def test_resplit_basis_is_gauge_invariant():
+    from oracle import trg
+    rng = np.random.default_rng(22)
+    dims = (2, 3, 2, 2)
+    f = int(np.prod(dims))
+    u, _ = np.linalg.qr(rng.standard_normal((f, 5)))
+    v, _ = np.linalg.qr(rng.standard_normal((f, 5)))
+    s = np.array([2.0, 1.0, 1.0, 0.3, 0.3])          # two degenerate pairs
+    g = rng.standard_normal((5, 5)) + 3 * np.eye(5)
+    phi1 = (u * s).reshape(dims + (5,))
+    psi1 = v.reshape(dims + (5,))
+    phi2 = (u * s @ g).reshape(dims + (5,))
+    psi2 = (v @ np.linalg.inv(g).T).reshape(dims + (5,))
+    a1, b1, _c1, d1, _, _ = trg.resplit(phi1, psi1, 1e-14)
+    a2, b2, _c2, d2, _, _ = trg.resplit(phi2, psi2, 1e-14)
+    assert np.max(np.abs(a1 - a2)) < 1e-12
+    assert np.max(np.abs(d1 - d2)) < 1e-12
+    assert np.max(np.abs(a1 @ b1.T - (u * s) @ v.T / 2.0)) < 1e-13
