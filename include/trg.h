@@ -60,14 +60,14 @@ typedef struct trg_options {
     uint32_t instance;  /* Philox counter word 2 (distinguishes independent solves)                */
     int precision;      /* TRG_FP64 / TRG_FP32 / TRG_BF16X3 / TRG_BF16X6                           */
     int bond_svd;       /* TRG_SVD_SKETCH / TRG_SVD_EXACT                                          */
-    int max_sweeps;     /* Jacobi sweep limit (0: default 60)                                       */
+    int max_sweeps;     /* Jacobi sweep limit (0: default 300)                                      */
     size_t workspace_cap; /* bytes of device workspace the state may hold (0: unlimited)           */
     void *stream;       /* hipStream_t to enqueue on, or NULL for the null stream                  */
     int device;         /* HIP device ordinal                                                      */
 } trg_options;
 
 /* Fills *opt with the defaults: dim 4, r 7, sketch_mult 2, power_iters 1,
- * seed 0, instance 0, FP64, sketch, max_sweeps 60, no cap, NULL stream,
+ * seed 0, instance 0, FP64, sketch, max_sweeps 300, no cap, NULL stream,
  * device 0. */
 void trg_default_options(trg_options *opt);
 
@@ -160,6 +160,12 @@ int trg_selftest_tsqr(int m, int n, const double *A, double *Q, double *R);
 /* One-sided Jacobi SVD of A (m x n, m >= n): U (m x n), s (n) descending,
  * V (n x n).  Returns the number of sweeps in *sweeps. */
 int trg_selftest_svd(int m, int n, const double *A, double *U, double *s, double *V, int *sweeps);
+
+/* Two-sided block Jacobi eigen-decomposition of `count` symmetric n x n
+ * matrices K (batch stride n*n; symmetrised on load): lam (count x n)
+ * descending, V (count x n x n) with eigenvector j in column j.  Returns the
+ * number of sweeps in *sweeps. */
+int trg_selftest_eigh(int count, int n, const double *K, double *lam, double *V, int *sweeps);
 
 /* Gaussian sketch entries Omega[beta, j1, j2, j3, m] (layout as named) drawn
  * exactly as the bond swap of step `step` draws them. */

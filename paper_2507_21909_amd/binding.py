@@ -76,10 +76,11 @@ def load_library(path=None):
     lib.trg_selftest_gemm.argtypes = [ctypes.c_int] * 7 + [_DP, _DP, _DP]
     lib.trg_selftest_tsqr.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP]
     lib.trg_selftest_svd.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP, _DP, ctypes.POINTER(ctypes.c_int)]
+    lib.trg_selftest_eigh.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP, ctypes.POINTER(ctypes.c_int)]
     lib.trg_selftest_sketch.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32] + [ctypes.c_int] * 5 + [_DP]
     for f in ("trg_create", "trg_destroy", "tensor_init", "atrg_step", "triad_atrg_step", "log_z_per_site",
               "trg_shape", "trg_export", "trg_set_timing", "trg_kernel_time", "trg_selftest_gemm",
-              "trg_selftest_tsqr", "trg_selftest_svd", "trg_selftest_sketch"):
+              "trg_selftest_tsqr", "trg_selftest_svd", "trg_selftest_eigh", "trg_selftest_sketch"):
         getattr(lib, f).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -100,7 +101,7 @@ class Solver:
     """One ATRG / triad-ATRG solve on one GPU (a trg_state)."""
 
     def __init__(self, dim=4, r=7, sketch_mult=2, power_iters=1, seed=0, instance=0, precision=FP64,
-                 bond_svd=SVD_SKETCH, max_sweeps=60, workspace_cap=0, stream=None, device=0):
+                 bond_svd=SVD_SKETCH, max_sweeps=0, workspace_cap=0, stream=None, device=0):
         lib = load_library()
         o = Options()
         lib.trg_default_options(ctypes.byref(o))
@@ -193,6 +194,22 @@ def selftest_svd(a):
     sw = ctypes.c_int()
     _check(lib.trg_selftest_svd(m, n, _p(a), _p(u), _p(s), _p(v), ctypes.byref(sw)))
     return u, s, v, sw.value
+
+
+def selftest_eigh(k):
+    """Eigen-decomposition of symmetric matrices k (n x n or count x n x n)."""
+    lib = load_library()
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    single = k.ndim == 2
+    kb = k[None] if single else k
+    count, n = kb.shape[0], kb.shape[1]
+    if kb.shape[2] != n:
+        raise ValueError("square matrices required")
+    lam = np.empty((count, n))
+    v = np.empty((count, n, n))
+    sw = ctypes.c_int(0)
+    _check(lib.trg_selftest_eigh(count, n, _p(kb), _p(lam), _p(v), ctypes.byref(sw)))
+    return (lam[0], v[0], sw.value) if single else (lam, v, sw.value)
 
 
 def selftest_sketch(seed, step, instance, chi, jdims, m):

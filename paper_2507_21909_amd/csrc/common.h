@@ -102,6 +102,14 @@ int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *wo
 // After jacobi_svd: s (count x n) descending singular values, U columns normalized
 // and sorted into u_sorted (row-major m x n, may be null), V sorted into v_sorted
 // (row-major n x n).
+// Symmetric eigen-decomposition (two-sided block Jacobi) of `count` n x n
+// matrices K (row-major, symmetrised on load): lam (count x n) descending,
+// vec (count x n x n) row-major with eigenvector j in column j.  ws / iws:
+// device scratch of eigh_ws_doubles / eigh_iws_ints entries.  Returns sweeps.
+size_t eigh_ws_doubles(int count, int n);
+size_t eigh_iws_ints(int count, int n);
+int eigh_sym(const double *K, int count, int n, double *lam, double *vec, double *ws, int *iws, int max_sweeps,
+             hipStream_t st);
 void jacobi_finish(const JacobiBatch &jb, double *s, double *u_sorted, double *v_sorted,
                    double *work, hipStream_t st);
 

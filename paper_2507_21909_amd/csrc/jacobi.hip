@@ -13,6 +13,8 @@
 // batch together.  Small n: one workgroup per matrix loops over every round
 // and sweep in a single launch.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -28,11 +30,12 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// rotate pair k of round r of matrix (u, v); returns true if rotated
-__device__ bool rotate_pair(double *u, double *v, int m, int n, int mm, int r, int k, double tol) {
+// rotate pair k of round r of matrix (u, v); returns 1 if rotated, 2 if the
+// pair's dot products are not finite (the pair is then left alone), else 0
+__device__ int rotate_pair(double *u, double *v, int m, int n, int mm, int r, int k, double tol) {
     const int lane = threadIdx.x & 63;
     int a = player_at(mm, k, r), b = player_at(mm, mm - 1 - k, r);
-    if (a >= n || b >= n) return false;
+    if (a >= n || b >= n) return 0;
     int p = a < b ? a : b, q = a < b ? b : a;
     double *up = u + (long)p * m, *uq = u + (long)q * m;
     double al = 0.0, be = 0.0, ga = 0.0;
@@ -45,7 +48,8 @@ __device__ bool rotate_pair(double *u, double *v, int m, int n, int mm, int r, i
     al = wave_sum(al);
     be = wave_sum(be);
     ga = wave_sum(ga);
-    if (al < 1e-280 || be < 1e-280 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) return false;
+    if (!isfinite(al + be + ga)) return 2;
+    if (al < 1e-280 || be < 1e-280 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) return 0;
     double zeta = (be - al) / (2.0 * ga);
     double t = zeta == 0.0 ? 1.0 : copysign(1.0, zeta) / (fabs(zeta) + hypot(zeta, 1.0));
     double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
@@ -60,9 +64,10 @@ __device__ bool rotate_pair(double *u, double *v, int m, int n, int mm, int r, i
         vp[i] = c * x - s * y;
         vq[i] = s * x + c * y;
     }
-    return true;
+    return 1;
 }
 
+// flags[mat]: rotations of this sweep; flags[count + mat]: non-finite pairs seen
 __global__ __launch_bounds__(NT) void round_kernel(JacobiBatch jb, int r, double tol, int *flags) {
     const int mat = blockIdx.y;
     const int k = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
@@ -70,7 +75,11 @@ __global__ __launch_bounds__(NT) void round_kernel(JacobiBatch jb, int r, double
     if (k >= mm / 2) return;
     double *u = jb.ut + (long)mat * jb.strideU;
     double *v = jb.vt + (long)mat * jb.strideV;
-    if (rotate_pair(u, v, jb.m, jb.n, mm, r, k, tol) && (threadIdx.x & 63) == 0) flags[mat] = 1;
+    const int rc = rotate_pair(u, v, jb.m, jb.n, mm, r, k, tol);
+    if ((threadIdx.x & 63) == 0) {
+        if (rc == 1) atomicAdd(&flags[mat], 1);
+        if (rc == 2) flags[jb.count + mat] = 1;
+    }
 }
 
 __global__ __launch_bounds__(NT) void full_kernel(JacobiBatch jb, int max_sweeps, double tol, int *flags) {
@@ -79,20 +88,30 @@ __global__ __launch_bounds__(NT) void full_kernel(JacobiBatch jb, int max_sweeps
     double *v = jb.vt + (long)mat * jb.strideV;
     const int mm = jb.n + (jb.n & 1);
     const int w = threadIdx.x >> 6;
-    __shared__ int rot;
+    __shared__ int rot, bad;
+    if (threadIdx.x == 0) bad = 0;
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
         if (threadIdx.x == 0) rot = 0;
         __syncthreads();
         for (int r = 0; r < mm - 1; ++r) {
-            for (int k = w; k < mm / 2; k += NT / 64)
-                if (rotate_pair(u, v, jb.m, jb.n, mm, r, k, tol) && (threadIdx.x & 63) == 0) rot = 1;
+            for (int k = w; k < mm / 2; k += NT / 64) {
+                const int rc = rotate_pair(u, v, jb.m, jb.n, mm, r, k, tol);
+                if ((threadIdx.x & 63) == 0) {
+                    if (rc == 1) atomicAdd(&rot, 1);
+                    if (rc == 2) bad = 1;
+                }
+            }
             __syncthreads();
         }
         if (rot == 0) break;
         __syncthreads();
     }
-    if (threadIdx.x == 0) flags[mat] = sweep < max_sweeps ? sweep : -1;
+    // flags[mat]: sweeps used (-1 - rotations of the last sweep if not converged)
+    if (threadIdx.x == 0) {
+        flags[mat] = sweep < max_sweeps ? sweep : -1 - rot;
+        flags[jb.count + mat] = bad;
+    }
 }
 
 __global__ void init_v_kernel(JacobiBatch jb) {
@@ -166,6 +185,35 @@ __global__ void sort_gather_kernel(JacobiBatch jb, const double *scale, const do
 }
 }  // namespace
 
+namespace {
+// sweep statistics of every call, printed when TRG_JACOBI_TRACE is set
+bool trace_on() {
+    static int on = -1;
+    if (on < 0) {
+        const char *e = getenv("TRG_JACOBI_TRACE");
+        on = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return on == 1;
+}
+
+[[noreturn]] void not_converged(const JacobiBatch &jb, const std::vector<int> &fl, bool full_path) {
+    char msg[256];
+    int stuck = 0, nonfinite = 0, worst_rot = 0;
+    for (int i = 0; i < jb.count; ++i) {
+        nonfinite += fl[jb.count + i] != 0;
+        int rot = full_path ? (fl[i] < 0 ? -1 - fl[i] : 0) : fl[i];
+        stuck += rot > 0;
+        worst_rot = std::max(worst_rot, rot);
+    }
+    snprintf(msg, sizeof msg,
+             "Jacobi SVD did not converge: %d of %d matrices (m %d, n %d) still rotating, up to %d "
+             "rotations in the last sweep; %d with non-finite entries",
+             stuck, jb.count, jb.m, jb.n, worst_rot, nonfinite);
+    throw Error(-4, msg);
+}
+}  // namespace
+
+// flags_dev: 2 * count ints of device scratch
 int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *work, hipStream_t st) {
     if (jb.count == 0 || jb.n == 0) return 0;
     const double tol = sqrt((double)jb.m) * 2.220446049250313e-16;
@@ -173,29 +221,40 @@ int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *wo
     hipLaunchKernelGGL(init_v_kernel, dim3(cdiv((size_t)jb.count * jb.n * jb.n, 256)), dim3(256), 0, st, jb);
     TRG_HIP_CHECK(hipGetLastError());
     const int mm = jb.n + (jb.n & 1);
-    std::vector<int> fl(jb.count);
+    std::vector<int> fl(2 * jb.count);
     if (jb.n <= 96) {
         hipLaunchKernelGGL(full_kernel, dim3(jb.count), dim3(NT), 0, st, jb, max_sweeps, tol, flags_dev);
         TRG_HIP_CHECK(hipGetLastError());
-        TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), flags_dev, sizeof(int) * jb.count, hipMemcpyDeviceToHost, st));
+        TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), flags_dev, sizeof(int) * 2 * jb.count, hipMemcpyDeviceToHost, st));
         TRG_HIP_CHECK(hipStreamSynchronize(st));
         int worst = 0;
-        for (int f : fl) {
-            TRG_REQUIRE(f >= 0, -4, "Jacobi SVD did not converge");
-            worst = std::max(worst, f);
+        bool bad = false;
+        for (int i = 0; i < jb.count; ++i) {
+            bad |= fl[i] < 0 || fl[jb.count + i] != 0;
+            worst = std::max(worst, fl[i]);
         }
+        if (trace_on()) fprintf(stderr, "[jacobi] count %d m %d n %d sweeps %d (one launch)\n", jb.count, jb.m, jb.n, worst);
+        if (bad) not_converged(jb, fl, true);
         return worst;
     }
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        TRG_HIP_CHECK(hipMemsetAsync(flags_dev, 0, sizeof(int) * jb.count, st));
+        TRG_HIP_CHECK(hipMemsetAsync(flags_dev, 0, sizeof(int) * 2 * jb.count, st));
         dim3 grid(cdiv(mm / 2, NT / 64), jb.count);
         for (int r = 0; r < mm - 1; ++r) hipLaunchKernelGGL(round_kernel, grid, dim3(NT), 0, st, jb, r, tol, flags_dev);
         TRG_HIP_CHECK(hipGetLastError());
-        TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), flags_dev, sizeof(int) * jb.count, hipMemcpyDeviceToHost, st));
+        TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), flags_dev, sizeof(int) * 2 * jb.count, hipMemcpyDeviceToHost, st));
         TRG_HIP_CHECK(hipStreamSynchronize(st));
-        bool any = false;
-        for (int f : fl) any |= f != 0;
+        bool any = false, bad = false;
+        long tot = 0;
+        for (int i = 0; i < jb.count; ++i) {
+            any |= fl[i] != 0;
+            bad |= fl[jb.count + i] != 0;
+            tot += fl[i];
+        }
+        if (trace_on()) fprintf(stderr, "[jacobi] count %d m %d n %d sweep %d rotations %ld\n", jb.count, jb.m, jb.n, sweep, tot);
+        if (bad) not_converged(jb, fl, false);
         if (!any) return sweep;
+        if (sweep + 1 == max_sweeps) not_converged(jb, fl, false);
     }
     throw Error(-4, "Jacobi SVD did not converge");
 }

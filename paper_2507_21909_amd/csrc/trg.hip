@@ -27,7 +27,7 @@ struct trg_state {
     double *phi = nullptr, *psi = nullptr;   // persistent state
     size_t cap_state = 0;
     double *dscal = nullptr;   // [0] logacc, [1] trace, [2..] scratch
-    int *dint = nullptr;       // [0] numerical status, [1..] flags / counts
+    int *dint = nullptr;       // [0] numerical status, [8..] kept counts
     std::vector<double> sigma_last;
     std::string err;
     bool timing = false;
@@ -169,9 +169,10 @@ void svd_colmajor(Step &T, const double *a, int count, int m, int n, double *s, 
     copy(ut, a, (size_t)count * m * n, c.st);
     double *vt = c.ar->dalloc((size_t)count * n * n);
     double *work = c.ar->dalloc((size_t)count * (n + 1));
+    int *flags = reinterpret_cast<int *>(c.ar->dalloc((size_t)count));   // 2 * count ints
     JacobiBatch jb{count, m, n, ut, vt, (long)m * n, (long)n * n};
-    int ms = T.S->opt.max_sweeps > 0 ? T.S->opt.max_sweeps : 60;
-    jacobi_svd(jb, ms, T.S->dint + 1, work, c.st);
+    int ms = T.S->opt.max_sweeps > 0 ? T.S->opt.max_sweeps : 300;
+    jacobi_svd(jb, ms, flags, work, c.st);
     jacobi_finish(jb, s, u, v, work, c.st);
 }
 
@@ -184,7 +185,11 @@ void svd_rowmajor(Step &T, const DT &a, double *s, double *u, double *v) {
 
 // eigen-decomposition of symmetric PSD matrices (count x n x n): lam desc, vecs row-major
 void eig_psd(Step &T, const double *k, int count, int n, double *lam, double *vec) {
-    svd_colmajor(T, k, count, n, n, lam, nullptr, vec);
+    Ctx &c = T.c;
+    double *ws = c.ar->dalloc(eigh_ws_doubles(count, n));
+    int *iws = reinterpret_cast<int *>(c.ar->dalloc((eigh_iws_ints(count, n) + 1) / 2));
+    int ms = T.S->opt.max_sweeps > 0 ? T.S->opt.max_sweeps : 300;
+    eigh_sym(k, count, n, lam, vec, ws, iws, ms, c.st);
 }
 
 // ---------------------------------------------------------------- re-split
@@ -813,7 +818,7 @@ void trg_default_options(trg_options *o) {
     o->power_iters = 1;
     o->precision = TRG_FP64;
     o->bond_svd = TRG_SVD_SKETCH;
-    o->max_sweeps = 60;
+    o->max_sweeps = 300;
 }
 
 int trg_create(const trg_options *opt, trg_state **out) {
@@ -1117,6 +1122,26 @@ int trg_selftest_svd(int m, int n, const double *A, double *U, double *S, double
         s.down(U, us, (size_t)m * n);
         s.down(S, sv, n);
         s.down(V, vs, (size_t)n * n);
+        if (sweeps) *sweeps = sw;
+    } catch (const Error &e) {
+        g_err = e.what();
+        return e.code;
+    }
+    return TRG_OK;
+}
+
+int trg_selftest_eigh(int count, int n, const double *K, double *lam, double *V, int *sweeps) {
+    if (!K || !lam || !V || n < 1 || count < 1) return TRG_E_INVALID;
+    try {
+        Scratch s;
+        const size_t nn = (size_t)count * n * n;
+        double *k = s.up(K, nn);
+        double *l = s.ar.dalloc((size_t)count * n), *v = s.ar.dalloc(nn);
+        double *ws = s.ar.dalloc(trg::eigh_ws_doubles(count, n));
+        int *iws = static_cast<int *>(s.ar.alloc(trg::eigh_iws_ints(count, n) * sizeof(int)));
+        int sw = trg::eigh_sym(k, count, n, l, v, ws, iws, 100, nullptr);
+        s.down(lam, l, (size_t)count * n);
+        s.down(V, v, nn);
         if (sweeps) *sweeps = sw;
     } catch (const Error &e) {
         g_err = e.what();

@@ -82,6 +82,59 @@ def test_jacobi_svd_graded_psd_eigen():
         assert abs(abs(v[:, j] @ q[:, j]) - 1.0) < 1e-10
 
 
+@pytest.mark.parametrize("n,count", [(1, 1), (5, 2), (64, 1), (65, 3), (100, 2), (256, 1), (300, 2)])
+def test_block_jacobi_eigh(n, count):
+    _say("eigh", n, count)
+    rng = np.random.default_rng(n * 13 + count)
+    x = rng.standard_normal((count, n, n))
+    k = x + x.transpose(0, 2, 1)
+    lam, v, sweeps = trg.selftest_eigh(k)
+    for b in range(count):
+        ref = np.linalg.eigvalsh(k[b])[::-1]
+        scale = np.max(np.abs(ref))
+        assert np.max(np.abs(lam[b] - ref)) < 20 * n * 2.2e-16 * scale
+        assert np.all(np.diff(lam[b]) <= 0)
+        assert np.max(np.abs(v[b].T @ v[b] - np.eye(n))) < 1e-12
+        assert np.max(np.abs(k[b] @ v[b] - v[b] * lam[b])) < 20 * n * 2.2e-16 * scale
+    assert sweeps < 30
+
+
+def test_block_jacobi_eigh_graded_and_rank_deficient_gram():
+    """A Gram X X^T of rank 120 in 520 dims with a spectrum graded over 12 decades:
+    the shape of the triad and squeezer Grams (most eigenvalues at the rounding floor)."""
+    rng = np.random.default_rng(31)
+    n, k = 520, 120
+    qx, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    sv = 10.0 ** -np.linspace(0, 6, k)
+    g = (qx * sv ** 2) @ qx.T
+    lam, v, sweeps = trg.selftest_eigh(g)
+    assert sweeps < 30
+    # g itself carries rounding noise of order n eps (its null space is not exact)
+    ref = np.linalg.eigvalsh(g)[::-1]
+    floor = 20 * n * 2.2e-16
+    assert np.max(np.abs(lam - ref)) < floor
+    assert np.max(np.abs(lam[:k] - sv ** 2)) < floor
+    assert np.max(np.abs(lam[k:])) < floor
+    # eigenvectors up to sign where the gap (about 0.2 lambda_j) dwarfs g's own noise
+    for j in range(0, k, 7):
+        if sv[j] ** 2 > 1e-4:
+            assert abs(abs(v[:, j] @ qx[:, j]) - 1.0) < 1e-8
+    assert np.max(np.abs(v.T @ v - np.eye(n))) < 1e-12
+
+
+def test_block_jacobi_eigh_degenerate():
+    rng = np.random.default_rng(32)
+    n = 130
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam0 = np.repeat([4.0, 2.0, 1.0, 0.5, 0.0], [3, 40, 1, 60, 26])
+    k = (q * lam0) @ q.T
+    lam, v, _ = trg.selftest_eigh(k)
+    assert np.max(np.abs(lam - lam0)) < 1e-13
+    p = v[:, 3:43] @ v[:, 3:43].T
+    p0 = q[:, 3:43] @ q[:, 3:43].T
+    assert np.max(np.abs(p - p0)) < 1e-12
+
+
 def test_sketch_matches_oracle():
     _say("sketch")
     g = trg.selftest_sketch(0x2507219090000000, 5, 3, 7, (5, 4, 3), 9)
