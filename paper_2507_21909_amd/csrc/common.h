@@ -54,6 +54,8 @@ void permute(const double *src, double *dst, const std::vector<int> &dims,
 void scale_axis(double *t, const std::vector<int> &dims, int axis, const double *v,
                 int mode, hipStream_t st);
 void fill(double *p, size_t n, double v, hipStream_t st);
+// C[r * sCr + c * sCn] = sum over s of w[s][r][c] (w: nslices x M x N), fixed order
+void sum_slices(const double *w, int nslices, long M, long N, double *C, long sCr, long sCn, hipStream_t st);
 void copy(double *dst, const double *src, size_t n, hipStream_t st);
 
 // ---- small device helpers (kernels.hip) ---------------------------------------------

@@ -114,6 +114,217 @@ __global__ __launch_bounds__(NT) void full_kernel(JacobiBatch jb, int max_sweeps
     }
 }
 
+// ---- panel variant (n > 96, m <= 1024) ------------------------------------
+// The columns are cut into blocks of 8; a round of the circle-method tournament
+// over the blocks pairs them, and one workgroup takes the 16-column panel of a
+// block pair with its m rows held in registers (row t + 256 j of every panel
+// column in thread t).  Inside the panel, cyclic one-sided Jacobi runs up to
+// max_inner sweeps of 15 parallel rounds of 8 disjoint column pairs, the
+// round-robin played on slots: slots k and 15 - k meet, then the columns in
+// slots 1..15 move one slot on (register moves), so every register index is a
+// compile-time constant and 15 rounds bring each column back to its slot.
+// The dot products are per-thread partial sums reduced across the wavefront by
+// a reduce-scatter butterfly and across the 4 wavefronts in LDS; the rotations
+// use the same formulas and threshold as rotate_pair.  The panel's rotations
+// are accumulated in a 16 x 16 matrix and applied to the 16 columns of V at
+// the end.  HBM sees each panel once per tournament round instead of once per
+// pair round, and a sweep needs nb - 1 launches instead of n - 1.
+constexpr int PW = 16;
+constexpr int PANEL_INNER = 1;   // inner sweeps per panel and tournament round
+
+template <int ROWS>
+__device__ inline void shift_slots(double (&u)[PW][ROWS], double (&vrow)[PW]) {
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) {
+        const double tmp = u[PW - 1][j];
+#pragma unroll
+        for (int c = PW - 1; c > 1; --c) u[c][j] = u[c - 1][j];
+        u[1][j] = tmp;
+    }
+    const double tmp = vrow[PW - 1];
+#pragma unroll
+    for (int c = PW - 1; c > 1; --c) vrow[c] = vrow[c - 1];
+    vrow[1] = tmp;
+}
+
+template <int ROWS>
+__global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r, double tol, int max_inner,
+                                                   int *flags) {
+    const int k = blockIdx.x, mat = blockIdx.y, t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int I = player_at(nb, k, r), J = player_at(nb, nb - 1 - k, r);
+    double *U = jb.ut + (long)mat * jb.strideU;
+    double *V = jb.vt + (long)mat * jb.strideV;
+    const int m = jb.m, n = jb.n;
+    __shared__ double red[NT / 64][24];
+    __shared__ double rc[8], rs[8];
+    __shared__ double vpan[PW][PW + 1];
+    __shared__ int sweep_rot, total_rot, nonfinite;
+
+    double u[PW][ROWS];
+#pragma unroll
+    for (int c = 0; c < PW; ++c) {
+        const int g = c < 8 ? I * 8 + c : J * 8 + (c - 8);
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const int row = t + NT * j;
+            u[c][j] = (g < n && row < m) ? U[(long)g * m + row] : 0.0;
+        }
+    }
+    double vrow[PW];
+#pragma unroll
+    for (int c = 0; c < PW; ++c) vrow[c] = c == t ? 1.0 : 0.0;
+    if (t == 0) {
+        sweep_rot = 0;
+        total_rot = 0;
+        nonfinite = 0;
+    }
+    __syncthreads();
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+    const int slot = (b5 ? 12 : 0) + (b4 ? 6 : 0) + (b3 ? 3 : 0);
+    for (int sw = 0; sw < max_inner; ++sw) {
+        for (int rr = 0; rr < PW - 1; ++rr) {
+            double v[24];
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int j = 0; j < ROWS; ++j) {
+                    al += u[kk][j] * u[kk][j];
+                    be += u[PW - 1 - kk][j] * u[PW - 1 - kk][j];
+                    ga += u[kk][j] * u[PW - 1 - kk][j];
+                }
+                v[3 * kk] = al;
+                v[3 * kk + 1] = be;
+                v[3 * kk + 2] = ga;
+            }
+            // reduce-scatter: after the xor-32/16/8 steps a lane holds 3 of the 24
+            // sums (slots `slot` .. slot + 2) over 8 lanes; xor 4/2/1 completes them
+            double w12[12], w6[6], w3[3];
+#pragma unroll
+            for (int i = 0; i < 12; ++i) {
+                const double send = b5 ? v[i] : v[12 + i], keep = b5 ? v[12 + i] : v[i];
+                w12[i] = keep + __shfl_xor(send, 32, 64);
+            }
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                const double send = b4 ? w12[i] : w12[6 + i], keep = b4 ? w12[6 + i] : w12[i];
+                w6[i] = keep + __shfl_xor(send, 16, 64);
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double send = b3 ? w6[i] : w6[3 + i], keep = b3 ? w6[3 + i] : w6[i];
+                w3[i] = keep + __shfl_xor(send, 8, 64);
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                w3[i] += __shfl_xor(w3[i], 4, 64);
+                w3[i] += __shfl_xor(w3[i], 2, 64);
+                w3[i] += __shfl_xor(w3[i], 1, 64);
+            }
+            if ((lane & 7) == 0) {
+                red[w][slot] = w3[0];
+                red[w][slot + 1] = w3[1];
+                red[w][slot + 2] = w3[2];
+            }
+            __syncthreads();
+            if (t < 8) {
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int x = 0; x < NT / 64; ++x) {
+                    al += red[x][3 * t];
+                    be += red[x][3 * t + 1];
+                    ga += red[x][3 * t + 2];
+                }
+                double c = 1.0, s = 0.0;
+                if (!isfinite(al + be + ga)) {
+                    nonfinite = 1;
+                } else if (!(al < 1e-280 || be < 1e-280 || fabs(ga) <= tol * sqrt(al) * sqrt(be))) {
+                    const double zeta = (be - al) / (2.0 * ga);
+                    const double tn = zeta == 0.0 ? 1.0 : copysign(1.0, zeta) / (fabs(zeta) + hypot(zeta, 1.0));
+                    c = 1.0 / sqrt(1.0 + tn * tn);
+                    s = c * tn;
+                    atomicAdd(&sweep_rot, 1);
+                }
+                rc[t] = c;
+                rs[t] = s;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const double c = rc[kk], s = rs[kk];
+#pragma unroll
+                for (int j = 0; j < ROWS; ++j) {
+                    const double x = u[kk][j], y = u[PW - 1 - kk][j];
+                    u[kk][j] = c * x - s * y;
+                    u[PW - 1 - kk][j] = s * x + c * y;
+                }
+                const double x = vrow[kk], y = vrow[PW - 1 - kk];
+                vrow[kk] = c * x - s * y;
+                vrow[PW - 1 - kk] = s * x + c * y;
+            }
+            shift_slots<ROWS>(u, vrow);
+        }
+        const int more = sweep_rot;
+        __syncthreads();
+        if (t == 0) {
+            total_rot += more;
+            sweep_rot = 0;
+        }
+        if (!more) break;
+    }
+    __syncthreads();
+    const int total = total_rot;
+    if (t == 0) {
+        if (total > 0) atomicAdd(&flags[mat], total);
+        if (nonfinite) flags[jb.count + mat] = 1;
+    }
+    if (total == 0) return;
+#pragma unroll
+    for (int c = 0; c < PW; ++c) {
+        const int g = c < 8 ? I * 8 + c : J * 8 + (c - 8);
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const int row = t + NT * j;
+            if (g < n && row < m) U[(long)g * m + row] = u[c][j];
+        }
+    }
+    if (t < PW) {
+#pragma unroll
+        for (int c = 0; c < PW; ++c) vpan[t][c] = vrow[c];
+    }
+    __syncthreads();
+    // V[:, panel] <- V[:, panel] * (panel rotation); thread t holds rows t + 256 j
+    // (n <= m, so ROWS covers them); each thread reads its rows before writing them
+    double vv[PW][ROWS];
+#pragma unroll
+    for (int c = 0; c < PW; ++c) {
+        const int g = c < 8 ? I * 8 + c : J * 8 + (c - 8);
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const int row = t + NT * j;
+            vv[c][j] = (g < n && row < n) ? V[(long)g * n + row] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < PW; ++c2) {
+        const int g = c2 < 8 ? I * 8 + c2 : J * 8 + (c2 - 8);
+        double acc[ROWS];
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) acc[j] = 0.0;
+#pragma unroll
+        for (int c = 0; c < PW; ++c) {
+            const double wv = vpan[c][c2];
+#pragma unroll
+            for (int j = 0; j < ROWS; ++j) acc[j] = fma(vv[c][j], wv, acc[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const int row = t + NT * j;
+            if (g < n && row < n) V[(long)g * n + row] = acc[j];
+        }
+    }
+}
+
 __global__ void init_v_kernel(JacobiBatch jb) {
     long tot = (long)jb.count * jb.n * jb.n;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
@@ -237,10 +448,25 @@ int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *wo
         if (bad) not_converged(jb, fl, true);
         return worst;
     }
+    const bool panel = jb.m <= 4 * NT;
+    const int nbk = ((jb.n + PW - 1) / PW) * PW / 8;   // blocks of 8 columns (even)
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         TRG_HIP_CHECK(hipMemsetAsync(flags_dev, 0, sizeof(int) * 2 * jb.count, st));
-        dim3 grid(cdiv(mm / 2, NT / 64), jb.count);
-        for (int r = 0; r < mm - 1; ++r) hipLaunchKernelGGL(round_kernel, grid, dim3(NT), 0, st, jb, r, tol, flags_dev);
+        if (panel) {
+            dim3 grid(nbk / 2, jb.count);
+            for (int r = 0; r < nbk - 1; ++r) {
+                if (jb.m <= NT)
+                    hipLaunchKernelGGL(panel_kernel<1>, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, flags_dev);
+                else if (jb.m <= 2 * NT)
+                    hipLaunchKernelGGL(panel_kernel<2>, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, flags_dev);
+                else
+                    hipLaunchKernelGGL(panel_kernel<4>, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, flags_dev);
+            }
+        } else {
+            dim3 grid(cdiv(mm / 2, NT / 64), jb.count);
+            for (int r = 0; r < mm - 1; ++r)
+                hipLaunchKernelGGL(round_kernel, grid, dim3(NT), 0, st, jb, r, tol, flags_dev);
+        }
         TRG_HIP_CHECK(hipGetLastError());
         TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), flags_dev, sizeof(int) * 2 * jb.count, hipMemcpyDeviceToHost, st));
         TRG_HIP_CHECK(hipStreamSynchronize(st));

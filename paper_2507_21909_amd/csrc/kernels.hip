@@ -314,6 +314,23 @@ void scale_axis(double *t, const std::vector<int> &dims, int axis, const double 
     TRG_HIP_CHECK(hipGetLastError());
 }
 
+namespace {
+__global__ void sum_slices_kernel(const double *w, int nslices, long M, long N, double *C, long sCr, long sCn) {
+    const long tot = M * N;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int s = 0; s < nslices; ++s) acc += w[(long)s * tot + e];
+        C[(e / N) * sCr + (e % N) * sCn] = acc;
+    }
+}
+}  // namespace
+
+void sum_slices(const double *w, int nslices, long M, long N, double *C, long sCr, long sCn, hipStream_t st) {
+    if (M * N == 0) return;
+    hipLaunchKernelGGL(sum_slices_kernel, dim3(grid_for(M * N)), dim3(256), 0, st, w, nslices, M, N, C, sCr, sCn);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
 void fill(double *p, size_t n, double v, hipStream_t st) {
     if (!n) return;
     hipLaunchKernelGGL(fill_kernel, dim3(grid_for((long)n)), dim3(256), 0, st, p, (long)n, v);

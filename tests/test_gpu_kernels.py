@@ -68,6 +68,36 @@ def test_jacobi_svd(m, n):
     assert sweeps < 40
 
 
+@pytest.mark.parametrize("m,n", [(1000, 517), (1024, 1024), (97, 97), (257, 130)])
+def test_panel_jacobi_svd(m, n):
+    """n > 96 runs the register-panel block Jacobi (rows per thread 1, 2 or 4)."""
+    _say("panel svd", m, n)
+    rng = np.random.default_rng(m + 3 * n)
+    a = rng.standard_normal((m, n))
+    u, s, v, sweeps = trg.selftest_svd(a)
+    ref = np.linalg.svd(a, compute_uv=False)
+    assert np.max(np.abs(s - ref)) < 1e-13 * ref[0] * np.sqrt(n)
+    assert np.max(np.abs(u @ np.diag(s) @ v.T - a)) < 1e-13 * ref[0] * np.sqrt(n)
+    assert np.max(np.abs(v.T @ v - np.eye(n))) < 1e-13 * np.sqrt(n)
+    assert np.max(np.abs(u.T @ u - np.eye(n))) < 1e-12 * np.sqrt(n)
+    assert sweeps < 40
+
+
+def test_panel_jacobi_svd_squeezer_shape():
+    """M = Df C Db (C orthogonal, Df, Db graded over 7 decades), the shape of the
+    squeezer matrix: the leading singular values keep high relative accuracy."""
+    rng = np.random.default_rng(77)
+    n = 1024
+    c, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    df = 10.0 ** -np.linspace(0, 7, n)
+    db = 10.0 ** -np.linspace(0, 7, n)[rng.permutation(n)]
+    a = (df[:, None] * c) * db[None, :]
+    u, s, v, _ = trg.selftest_svd(a)
+    ref = np.linalg.svd(a, compute_uv=False)
+    assert np.max(np.abs(s[:40] - ref[:40]) / ref[:40]) < 1e-12
+    assert np.max(np.abs(u[:, :40] * s[:40] - a @ v[:, :40])) < 1e-13 * s[0]
+
+
 def test_jacobi_svd_graded_psd_eigen():
     rng = np.random.default_rng(9)
     n = 150
@@ -76,7 +106,11 @@ def test_jacobi_svd_graded_psd_eigen():
     k = (q * lam) @ q.T
     k = 0.5 * (k + k.T)
     _u, s, v, _ = trg.selftest_svd(k)
-    assert np.max(np.abs(s - lam) / lam[0]) < 1e-13
+    # k carries its own rounding (about n eps): compare with LAPACK on the same k;
+    # the block (panel) Jacobi applies more, smaller rotations than the cyclic one
+    ref = np.linalg.svd(k, compute_uv=False)
+    assert np.max(np.abs(s - ref) / lam[0]) < 3e-13
+    assert np.max(np.abs(s - lam) / lam[0]) < 20 * n * 2.2e-16
     # leading eigenvectors (well separated) match up to sign
     for j in range(10):
         assert abs(abs(v[:, j] @ q[:, j]) - 1.0) < 1e-10
