@@ -41,10 +41,11 @@ struct GemmArgs {
     double *C; long sCr, sCn, sCb;
     double alpha, beta;
 };
-void gemm(const GemmArgs &g, Prec prec, hipStream_t st);
-void gemm_f64(const GemmArgs &g, hipStream_t st);
+// ev0 / ev1 (optional): events stamped at the kernel's start and end
+void gemm(const GemmArgs &g, Prec prec, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void gemm_f64(const GemmArgs &g, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // mode 1: FP32, 2: BF16 split, 3 products; 3: BF16 split, 6 products
-void gemm_mixed(const GemmArgs &g, int mode, hipStream_t st);
+void gemm_mixed(const GemmArgs &g, int mode, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // ---- element-wise / layout kernels (kernels.hip) -----------------------------------
 // dst = src with axes permuted: dst dims = src dims[perm[i]].

@@ -8,6 +8,8 @@
 // tile of C; its four wavefronts own 32x32 quadrants (2x2 MFMA tiles).  K is
 // staged through LDS in slabs of 16, K-major, and the next slab is fetched
 // into registers while the current one is multiplied.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace trg {
@@ -17,6 +19,9 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 namespace {
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256, LP = 4;  // LP: LDS row padding
 
+// TAG only names the instance: 1 for the timed coarse-graining contractions
+// (makeMG / makeMH), so a kernel trace separates them from the other GEMMs.
+template <int TAG>
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
     const int bz = blockIdx.z;
     const double *A = g.A + (long)bz * g.sAb;
@@ -106,7 +111,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
 }
 }  // namespace
 
-void gemm_f64(const GemmArgs &g, hipStream_t st) {
+void gemm_f64(const GemmArgs &g, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
     for (int b0 = 0; b0 < g.batch; b0 += 65535) {
         GemmArgs h = g;
@@ -115,7 +120,10 @@ void gemm_f64(const GemmArgs &g, hipStream_t st) {
         h.B += (long)b0 * g.sBb;
         h.C += (long)b0 * g.sCb;
         dim3 grid(cdiv(h.N, BN), cdiv(h.M, BM), h.batch);
-        hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, st, h);
+        if (ev0 && g.batch <= 65535)   // kernel start / end timestamps
+            hipExtLaunchKernelGGL(gemm_f64_kernel<1>, grid, dim3(NT), 0, st, ev0, ev1, 0, h);
+        else
+            hipLaunchKernelGGL(gemm_f64_kernel<0>, grid, dim3(NT), 0, st, h);
     }
     TRG_HIP_CHECK(hipGetLastError());
 }
@@ -348,7 +356,7 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(GemmArgs g) {
 }
 
 template <typename K>
-void launch_batched(K kern, const GemmArgs &g, hipStream_t st) {
+void launch_batched(K kern, const GemmArgs &g, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
     for (int b0 = 0; b0 < g.batch; b0 += 65535) {
         GemmArgs h = g;
@@ -357,18 +365,21 @@ void launch_batched(K kern, const GemmArgs &g, hipStream_t st) {
         h.B += (long)b0 * g.sBb;
         h.C += (long)b0 * g.sCb;
         dim3 grid(cdiv(h.N, BN), cdiv(h.M, BM), h.batch);
-        hipLaunchKernelGGL(kern, grid, dim3(NT), 0, st, h);
+        if (ev0 && g.batch <= 65535)
+            hipExtLaunchKernelGGL(kern, grid, dim3(NT), 0, st, ev0, ev1, 0, h);
+        else
+            hipLaunchKernelGGL(kern, grid, dim3(NT), 0, st, h);
     }
     TRG_HIP_CHECK(hipGetLastError());
 }
 }  // namespace
 
-void gemm_mixed(const GemmArgs &g, int mode, hipStream_t st) {
+void gemm_mixed(const GemmArgs &g, int mode, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     switch (mode) {
-        case 1: launch_batched(gemm_f32_kernel, g, st); break;
-        case 2: launch_batched(gemm_bf16_kernel<2, 3>, g, st); break;
-        case 3: launch_batched(gemm_bf16_kernel<3, 6>, g, st); break;
-        default: gemm_f64(g, st);
+        case 1: launch_batched(gemm_f32_kernel, g, st, ev0, ev1); break;
+        case 2: launch_batched(gemm_bf16_kernel<2, 3>, g, st, ev0, ev1); break;
+        case 3: launch_batched(gemm_bf16_kernel<3, 6>, g, st, ev0, ev1); break;
+        default: gemm_f64(g, st, ev0, ev1);
     }
 }
 

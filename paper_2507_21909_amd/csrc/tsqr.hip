@@ -2,12 +2,13 @@
 // the re-split QR(Phi), QR(Psi) (Fig. 5f), the QR of the bond-swap sketches
 // (App. A, eq. bond1 / bond2) and, in exact mode, the QR of B and C (App. A).
 //
-// Level l splits its rows into blocks of BR rows; one workgroup loads a block
-// into LDS, factors it with Householder reflections (LAPACK dlarfg / dlarf
-// order) and writes the n x n R factor and the explicit BR x n thin Q (dorg2r,
-// formed in place).  The stacked R factors are the next level's input; the
-// last level (one block) fixes diag(R) >= 0.  Q is then rebuilt top-down:
-// Q_l[block b] = Q_l,b * Q_{l+1}[b*n:(b+1)*n, :], a batched GEMM per level.
+// Level l splits its rows into blocks of 256 rows; one workgroup factors a
+// block with Householder reflections (LAPACK dlarfg / dlarf order), one row of
+// the block per thread held in registers, and writes the n x n R factor and
+// the explicit 256 x n thin Q (dorg2r order).  The stacked R factors are the
+// next level's input; the last level (one block) fixes diag(R) >= 0.  Q is
+// then rebuilt top-down: Q_l[block b] = Q_l,b * Q_{l+1}[b*n:(b+1)*n, :], a
+// batched GEMM per level.
 #include <cmath>
 
 #include "common.h"
@@ -17,136 +18,140 @@ namespace trg {
 namespace {
 constexpr int NT = 256;
 
-// LDS per workgroup available to one kernel (queried once; 64 KiB if unknown)
-size_t lds_limit() {
-    static size_t lim = 0;
-    if (!lim) {
-        int dev = 0, v = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
-            (void)hipGetLastError();
-            v = 65536;
+// Block factorisation: one row of the 256-row block per thread (NC >= n
+// columns in registers), Householder column by column with the dot products of
+// the reflector with every column (v^T A) reduced at once: a reduce-scatter
+// butterfly across the wavefront, then the 4 wavefronts in LDS.
+constexpr int RB = 256;   // rows per block
+
+// one halving step of the reduce-scatter: CNT live values in v[0..CNT), the
+// partner (lane ^ off) keeps the other half; all indices compile-time
+template <int NC, int CNT>
+__device__ inline void halve(double (&v)[NC], int lane, int &idx) {
+    if constexpr (CNT > 1) {
+        constexpr int half = CNT / 2, off = 32 * CNT / NC;
+        const bool hi = lane & off;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const double send = hi ? v[i] : v[half + i], keep = hi ? v[half + i] : v[i];
+            v[i] = keep + __shfl_xor(send, off, 64);
         }
-        lim = (size_t)v;
+        idx += hi ? half : 0;
+        halve<NC, half>(v, lane, idx);
     }
-    return lim;
 }
 
-inline size_t lds_bytes(int br, int n) { return ((size_t)br * n + 64 + 8 + 256) * sizeof(double) + 64 * sizeof(double); }
-
-// rows per block: the largest of 1024, 512, 256, 128, 64 (and >= n) whose tile fits in LDS
-inline int block_rows(int n) {
-    for (int br : {1024, 512, 256, 128, 64})
-        if (br >= n && lds_bytes(br, n) <= lds_limit() && (size_t)br * n <= 16384) return br;
-    return 64;
+// sum over the workgroup of v[0..NC) (per thread); result in out[0..NC) (LDS)
+template <int NC>
+__device__ inline void wg_sum(double (&v)[NC], double (*red)[NC], double *out) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int idx = 0;
+    halve<NC, NC>(v, lane, idx);
+    // v[0] holds value idx summed over the lanes that differ in the top bits;
+    // finish over the low 64 / NC lanes
+#pragma unroll
+    for (int off = (64 / NC) / 2; off > 0; off >>= 1) v[0] += __shfl_xor(v[0], off, 64);
+    if ((lane & (64 / NC - 1)) == 0) red[w][idx] = v[0];
+    __syncthreads();
+    if ((int)threadIdx.x < NC) out[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                                                 red[3][threadIdx.x];
+    __syncthreads();
 }
 
-__device__ double block_sum(double v, double *red) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) red[w] = v;
-    __syncthreads();
-    double s = red[0] + red[1] + red[2] + red[3];
-    return s;
-}
-
-// a: rows x n row-major (this level's input); block b covers rows [b*BR, b*BR+BR)
-__global__ __launch_bounds__(NT) void qr_block_kernel(const double *a, long rows, int n, int BR,
-                                                      double *rout,   // (nb*n) x n stacked R
-                                                      double *qout,   // nb x BR x n thin Q
-                                                      int final_level) {
-    extern __shared__ double lds[];
-    double *A = lds;                    // BR x n
-    double *tau = lds + (long)BR * n;   // n
-    double *red = tau + 64;             // 8
-    double *wv = red + 8;               // 4 x 64 partial dots
-    const int b = blockIdx.x;
-    const long r0 = (long)b * BR;
-    const int t = threadIdx.x;
-    for (int i = t; i < BR * n; i += NT) {
-        long r = r0 + i / n;
-        A[i] = r < rows ? a[r * n + (i % n)] : 0.0;
-    }
-    __syncthreads();
-    const int cc = t & 63, part = t >> 6;   // column / row-quarter for the dot products
+template <int NC>
+__global__ __launch_bounds__(NT) void qr_block_reg_kernel(const double *a_in, long rows, int n, double *rout,
+                                                          double *qout, int final_level) {
+    extern __shared__ double vl[];            // RB x NC: Householder vectors (below diag) and R
+    __shared__ double red[4][NC];
+    __shared__ double wsum[NC], taus[NC], dsg[NC];
+    __shared__ double ab[2];
+    const int t = threadIdx.x, b = blockIdx.x;
+    const long row = (long)b * RB + t;
+    double a[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) a[c] = (row < rows && c < n) ? a_in[row * n + c] : 0.0;
     for (int j = 0; j < n; ++j) {
-        // norm of A[j+1:, j]
-        double s = 0.0;
-        for (int i = j + 1 + t; i < BR; i += NT) s += A[i * n + j] * A[i * n + j];
-        double xnorm2 = block_sum(s, red);
-        double alpha = A[j * n + j];
-        double tj = 0.0, beta = alpha, scal = 0.0;
+        double x = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x = c == j ? a[c] : x;
+        // xnorm2 = sum_{i > j} x_i^2, alpha = x_j
+        {
+            double p2[2] = {t > j ? x * x : 0.0, t == j ? x : 0.0};
+            const int lane = t & 63, w = t >> 6;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                p2[0] += __shfl_xor(p2[0], off, 64);
+                p2[1] += __shfl_xor(p2[1], off, 64);
+            }
+            if (lane == 0) {
+                red[w][0] = p2[0];
+                red[w][1] = p2[1];
+            }
+            __syncthreads();
+            if (t < 2) ab[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+            __syncthreads();
+        }
+        const double xnorm2 = ab[0], alpha = ab[1];
+        double tau = 0.0, beta = alpha, scal = 0.0;
         if (xnorm2 > 0.0) {
-            double nrm = sqrt(alpha * alpha + xnorm2);
+            const double nrm = sqrt(alpha * alpha + xnorm2);
             beta = alpha >= 0.0 ? -nrm : nrm;
-            tj = (beta - alpha) / beta;
+            tau = (beta - alpha) / beta;
             scal = 1.0 / (alpha - beta);
         }
-        __syncthreads();
-        if (tj != 0.0)
-            for (int i = j + 1 + t; i < BR; i += NT) A[i * n + j] *= scal;
-        if (t == 0) { tau[j] = tj; A[j * n + j] = beta; }
-        __syncthreads();
-        if (tj == 0.0) continue;
-        // w_c = v^T A[j:, c], v = [1; A[j+1:, j]]
-        const int nc = n - j - 1;
-        if (cc < nc) {
-            const int c = j + 1 + cc;
-            double acc = 0.0;
-            for (int i = j + part; i < BR; i += 4) {
-                double vi = (i == j) ? 1.0 : A[i * n + j];
-                acc += vi * A[i * n + c];
-            }
-            wv[part * 64 + cc] = acc;
-        }
-        __syncthreads();
-        for (int idx = t; idx < (BR - j) * nc; idx += NT) {
-            int i = j + idx / nc, c = j + 1 + idx % nc;
-            double vi = (i == j) ? 1.0 : A[i * n + j];
-            double w = wv[c - j - 1] + wv[64 + c - j - 1] + wv[128 + c - j - 1] + wv[192 + c - j - 1];
-            A[i * n + c] -= tj * vi * w;
-        }
-        __syncthreads();
+        if (t == 0) taus[j] = tau;
+        double vt = 0.0;
+        if (t == j) vt = 1.0;
+        else if (t > j) vt = tau != 0.0 ? x * scal : x;
+        const double newx = t == j ? beta : (t > j ? vt : x);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) a[c] = c == j ? newx : a[c];
+        if (tau == 0.0) continue;   // uniform
+        double p[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) p[c] = vt * a[c];
+        wg_sum<NC>(p, red, wsum);
+        const double tv = tau * vt;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c > j) a[c] -= tv * wsum[c];
     }
-    // R (upper triangle), with the sign of the final level
-    __shared__ double dsg[64];
-    if (t < n) dsg[t] = (final_level && A[t * n + t] < 0.0) ? -1.0 : 1.0;
-    __syncthreads();
-    for (int i = t; i < n * n; i += NT) {
-        int r = i / n, c = i % n;
-        rout[((long)b * n + r) * n + c] = c >= r ? dsg[r] * A[r * n + c] : 0.0;
+    // R rows (thread t < n owns row t) with the final level's sign; vectors to LDS
+    if (t < n) {
+        double d = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) d = c == t ? a[c] : d;
+        dsg[t] = (final_level && d < 0.0) ? -1.0 : 1.0;
     }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) vl[t * NC + c] = a[c];
     __syncthreads();
-    // explicit thin Q in place (dorg2r)
+    if (t < n) {
+        const double sg = dsg[t];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < n) rout[((long)b * n + t) * n + c] = c >= t ? sg * a[c] : 0.0;
+    }
+    // explicit thin Q (dorg2r): Q = H_0 ... H_{n-1} [I; 0], row t in registers
+    double q[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) q[c] = (t == c && c < n) ? 1.0 : 0.0;
     for (int j = n - 1; j >= 0; --j) {
-        const double tj = tau[j];
-        const int nc = n - j - 1;
-        if (nc > 0) {
-            if (t == 0) A[j * n + j] = 1.0;
-            __syncthreads();
-            if (cc < nc && tj != 0.0) {
-                const int c = j + 1 + cc;
-                double acc = 0.0;
-                for (int i = j + part; i < BR; i += 4) acc += A[i * n + j] * A[i * n + c];
-                wv[part * 64 + cc] = acc;
-            }
-            __syncthreads();
-            if (tj != 0.0)
-                for (int idx = t; idx < (BR - j) * nc; idx += NT) {
-                    int i = j + idx / nc, c = j + 1 + idx % nc;
-                    double w = wv[c - j - 1] + wv[64 + c - j - 1] + wv[128 + c - j - 1] + wv[192 + c - j - 1];
-                    A[i * n + c] -= tj * A[i * n + j] * w;
-                }
-            __syncthreads();
-        }
-        for (int i = j + 1 + t; i < BR; i += NT) A[i * n + j] *= -tj;
-        if (t == 0) A[j * n + j] = 1.0 - tj;
-        for (int i = t; i < j; i += NT) A[i * n + j] = 0.0;
-        __syncthreads();
+        const double tau = taus[j];
+        if (tau == 0.0) continue;   // uniform
+        const double vt = t == j ? 1.0 : (t > j ? vl[t * NC + j] : 0.0);
+        double p[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) p[c] = vt * q[c];
+        wg_sum<NC>(p, red, wsum);
+        const double tv = tau * vt;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] -= tv * wsum[c];
     }
-    double *q = qout + (long)b * BR * n;
-    for (int i = t; i < BR * n; i += NT) q[i] = A[i] * dsg[i % n];
+    double *qo = qout + (long)b * RB * n;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (c < n) qo[(long)t * n + c] = q[c] * dsg[c];
 }
 
 struct Level {
@@ -158,7 +163,7 @@ struct Level {
 }  // namespace
 
 size_t tsqr_ws_doubles(long m, int n) {
-    const int BR = block_rows(n);
+    const int BR = RB;
     size_t tot = 0;
     long rows = m;
     while (true) {
@@ -173,19 +178,25 @@ size_t tsqr_ws_doubles(long m, int n) {
     return tot + 64;
 }
 
+namespace {
+template <int NC>
+void launch_block_reg(int nb, const double *in, long rows, int n, double *rs, double *q, bool fin, hipStream_t st) {
+    const size_t lds = (size_t)RB * NC * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(qr_block_reg_kernel<NC>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            (void)hipGetLastError();
+        attr = true;
+    }
+    hipLaunchKernelGGL(qr_block_reg_kernel<NC>, dim3(nb), dim3(NT), lds, st, in, rows, n, rs, q, fin ? 1 : 0);
+}
+}  // namespace
+
 void tsqr(const double *a, long m, int n, double *q, double *r, double *ws, hipStream_t st) {
     TRG_REQUIRE(n >= 1 && n <= 64, -6, "tsqr: n must be in [1, 64]");
     TRG_REQUIRE(m >= n, -6, "tsqr: needs m >= n");
-    const int BR = block_rows(n);
-    const size_t lds = ((size_t)BR * n + 64 + 8 + 256) * sizeof(double);
-    TRG_REQUIRE(lds_bytes(BR, n) <= lds_limit(), -6, "tsqr: LDS tile does not fit");
-    static size_t attr_set = 0;
-    if (lds > 65536 && lds > attr_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(qr_block_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-            (void)hipGetLastError();
-        attr_set = lds;
-    }
+    const int BR = RB;
     std::vector<Level> lv;
     double *p = ws;
     const double *in = a;
@@ -200,7 +211,9 @@ void tsqr(const double *a, long m, int n, double *q, double *r, double *ws, hipS
         double *rs = p;
         p += (size_t)L.nb * n * n;
         bool fin = L.nb == 1;
-        hipLaunchKernelGGL(qr_block_kernel, dim3(L.nb), dim3(NT), lds, st, in, rows, n, BR, rs, L.q, fin ? 1 : 0);
+        if (n <= 16) launch_block_reg<16>(L.nb, in, rows, n, rs, L.q, fin, st);
+        else if (n <= 32) launch_block_reg<32>(L.nb, in, rows, n, rs, L.q, fin, st);
+        else launch_block_reg<64>(L.nb, in, rows, n, rs, L.q, fin, st);
         TRG_HIP_CHECK(hipGetLastError());
         lv.push_back(L);
         if (fin) {
