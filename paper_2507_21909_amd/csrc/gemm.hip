@@ -21,30 +21,35 @@ constexpr int BM = 64, BN = 64, BK = 16, NT = 256, LP = 4;  // LP: LDS row paddi
 
 // TAG only names the instance: 1 for the timed coarse-graining contractions
 // (makeMG / makeMH), so a kernel trace separates them from the other GEMMs.
-template <int TAG>
+// TM: tile edge (64 or 128); each wavefront owns a (TM/2)^2 quadrant of
+// (TM/32)^2 MFMA tiles.  128 doubles the flops per byte staged (16 flop/B).
+template <int TAG, int TM>
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
+    constexpr int NI = TM / 32;            // MFMA tiles per wave and dimension
+    constexpr int EPT = TM * BK / NT;      // elements per thread per operand and K tile
+    constexpr int TPR = BK / EPT;          // threads per row (k-fast loads)
     const int bz = blockIdx.z;
     const double *A = g.A + (long)bz * g.sAb;
     const double *B = g.B + (long)bz * g.sBb;
     double *C = g.C + (long)bz * g.sCb;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
 
-    __shared__ double As[BK][BM + LP];
-    __shared__ double Bs[BK][BN + LP];
+    __shared__ double As[BK][TM + LP];
+    __shared__ double Bs[BK][TM + LP];
 
-    // loader mapping (4 elements per thread per operand)
+    // loader mapping (EPT elements per thread per operand)
     const bool a_kfast = (g.sAk == 1) || (g.sAr != 1);
     const bool b_nfast = (g.sBn == 1) || (g.sBk != 1);
-    int ar, ak, br, bk;  // base row/k of this thread's 4 A elements, k/col of B
-    if (a_kfast) { ar = t >> 2; ak = (t & 3) * 4; } else { ak = t >> 4; ar = (t & 15) * 4; }
-    if (b_nfast) { bk = t >> 4; br = (t & 15) * 4; } else { br = t >> 2; bk = (t & 3) * 4; }
+    int ar, ak, br, bk;  // base row/k of this thread's A elements, k/col of B
+    if (a_kfast) { ar = t / TPR; ak = (t % TPR) * EPT; } else { ak = t / (TM / EPT); ar = (t % (TM / EPT)) * EPT; }
+    if (b_nfast) { bk = t / (TM / EPT); br = (t % (TM / EPT)) * EPT; } else { br = t / TPR; bk = (t % TPR) * EPT; }
 
-    double ra[4], rb[4];
+    double ra[EPT], rb[EPT];
     auto load = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < EPT; ++i) {
             int r = m0 + (a_kfast ? ar : ar + i), k = k0 + (a_kfast ? ak + i : ak);
             ra[i] = (r < g.M && k < g.K) ? A[(long)r * g.sAr + (long)k * g.sAk] : 0.0;
             int c = n0 + (b_nfast ? br + i : br), kb = k0 + (b_nfast ? bk : bk + i);
@@ -53,17 +58,17 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
     };
     auto store = [&]() {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < EPT; ++i) {
             if (a_kfast) As[ak + i][ar] = ra[i]; else As[ak][ar + i] = ra[i];
             if (b_nfast) Bs[bk][br + i] = rb[i]; else Bs[bk + i][br] = rb[i];
         }
     };
 
-    d4 acc[2][2];
+    d4 acc[NI][NI];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < NI; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
     const int nk = (g.K + BK - 1) / BK;
     load(0);
@@ -74,15 +79,15 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int kr = kk + (lane >> 4);
-            double af[2], bf[2];
+            double af[NI], bf[NI];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) af[i] = As[kr][wr * 32 + i * 16 + (lane & 15)];
+            for (int i = 0; i < NI; ++i) af[i] = As[kr][wr * (TM / 2) + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bf[j] = Bs[kr][wc * 32 + j * 16 + (lane & 15)];
+            for (int j = 0; j < NI; ++j) bf[j] = Bs[kr][wc * (TM / 2) + j * 16 + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < NI; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < NI; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
@@ -94,13 +99,13 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
     // epilogue: item e of lane l holds D[l/16 + 4e][l%16] of each 16x16 tile
     // (the f64 16x16x4 output layout, checked against a host GEMM)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NI; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                int r = m0 + wr * 32 + i * 16 + (lane >> 4) + 4 * e;
-                int c = n0 + wc * 32 + j * 16 + (lane & 15);
+                int r = m0 + wr * (TM / 2) + i * 16 + (lane >> 4) + 4 * e;
+                int c = n0 + wc * (TM / 2) + j * 16 + (lane & 15);
                 if (r < g.M && c < g.N) {
                     double *p = C + (long)r * g.sCr + (long)c * g.sCn;
                     double v = g.alpha * acc[i][j][e];
@@ -119,11 +124,20 @@ void gemm_f64(const GemmArgs &g, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
         h.A += (long)b0 * g.sAb;
         h.B += (long)b0 * g.sBb;
         h.C += (long)b0 * g.sCb;
-        dim3 grid(cdiv(h.N, BN), cdiv(h.M, BM), h.batch);
-        if (ev0 && g.batch <= 65535)   // kernel start / end timestamps
-            hipExtLaunchKernelGGL(gemm_f64_kernel<1>, grid, dim3(NT), 0, st, ev0, ev1, 0, h);
-        else
-            hipLaunchKernelGGL(gemm_f64_kernel<0>, grid, dim3(NT), 0, st, h);
+        // 128-edge tiles measured slower than 64 on the coarse-graining shapes
+        // (one wavefront per SIMD at 218 VGPRs); kept selectable for tuning
+        constexpr bool kBigTiles = false;
+        const bool big = kBigTiles && h.M >= 256 && h.N >= 256 &&
+                         (long)cdiv(h.N, 128) * cdiv(h.M, 128) * h.batch >= 256;
+        const int tm = big ? 128 : 64;
+        dim3 grid(cdiv(h.N, tm), cdiv(h.M, tm), h.batch);
+        if (ev0 && g.batch <= 65535) {   // kernel start / end timestamps
+            if (big) hipExtLaunchKernelGGL(gemm_f64_kernel<1, 128>, grid, dim3(NT), 0, st, ev0, ev1, 0, h);
+            else hipExtLaunchKernelGGL(gemm_f64_kernel<1, 64>, grid, dim3(NT), 0, st, ev0, ev1, 0, h);
+        } else {
+            auto kern = big ? gemm_f64_kernel<0, 128> : gemm_f64_kernel<0, 64>;
+            hipLaunchKernelGGL(kern, grid, dim3(NT), 0, st, h);
+        }
     }
     TRG_HIP_CHECK(hipGetLastError());
 }
