@@ -8,8 +8,9 @@ timed steps continue the same flow.  Prints one JSON line.
 The roofline entry is for the coarse-graining GEMMs (makeMG / makeMH), the
 dominant kernel: algorithmic flops per launch (2 M N K of the contraction)
 over the launch's average duration from HIP events on the library's stream.
-The CPU baseline times the FP64 oracle on a bounded sample of the same step
-(see cpu_baseline.sample).
+The CPU baseline times one steady-state step of the FP64 oracle at D = 16 on
+the host and scales it to D by the step's algorithmic flop ratio (see
+cpu_baseline.sample).
 """
 import argparse
 import json
@@ -22,39 +23,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense MFMA TFLOP/s, MI355X
+# HBM bytes per makeMG/makeMH launch (FETCH_SIZE + WRITE_SIZE from two rocprofv3
+# --pmc runs of this benchmark, each scaled by the counter's reading for a plain
+# 1 GiB copy) for the FP64 kernel at D = 32, r = 7; None for other settings.
+TRAFFIC = {("fp64", 32, 7): 5.90e9}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
 
 
-def cpu_baseline(D, r):
-    """Time the oracle's makeMG at D, R = r D on 1 and 2 of the D i_a slabs.
+def cpu_baseline(D, r, beta, h, seed):
+    """Time one steady-state oracle step at D = 16 and scale it to D.
 
-    The marginal per-slab time (2 slabs minus 1) times D plus the slab-free
-    part (T23) gives Phi; Phi and Psi together are 85% of the algorithmic
-    flops of a steady step at D = 32, which scales the sample to one step.
+    The oracle (numpy FP64 with its own C Jacobi solvers) runs the same flow
+    (beta, h, r, seed) for 4 warm-up steps, until the leg dimensions saturate
+    at 16, then one timed step.  That step's time is scaled to D by the ratio
+    of the step's algorithmic flops: 8 R^2 D^5 (makeMG/makeMH) + 24 R^2 D^4
+    (squeezers) + 8 D^7 + 8 R D^5 (triad) + 8 D^7 + 4 D^7 (bond swap).
     """
-    import numpy as np
     from oracle import trg as otrg
-    R = r * D
-    rng = np.random.default_rng(0)
-    f = rng.standard_normal((D, R, D, D))           # F[alpha, kX, t3, g]
-    ti = rng.standard_normal((D, D, R))
-    tj = rng.standard_normal((D, D, R))
-    m = [rng.standard_normal((D, D, D)) for _ in range(3)]
+
+    def step_flops(d):
+        rr = r * d
+        return 8.0 * rr * rr * d ** 5 + 24.0 * rr * rr * d ** 4 + 8.0 * d ** 7 + 8.0 * rr * d ** 5 + 12.0 * d ** 7
+
+    d0 = 16
+    prm = otrg.Params(D=d0, r=r, seed=seed)
+    st = otrg.init_ising(beta, h, 4)
+    for i in range(4):
+        otrg.rg_step(st, i % 4, prm, "triad")
+    t0 = time.perf_counter()
+    otrg.rg_step(st, 4 % 4, prm, "triad")
+    t_step = time.perf_counter() - t0
+    scale = step_flops(D) / step_flops(d0)
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    times = []
-    for slabs in (1, 2):
-        e = rng.standard_normal((slabs, R, D, D))   # E[i_a, kA, t3, alpha] on `slabs` i_a values
-        t0 = time.perf_counter()
-        otrg.make_phi(e, f, ti, tj, *m)
-        times.append(time.perf_counter() - t0)
-    per_slab = max(times[1] - times[0], 1e-9)
-    fixed = max(times[0] - per_slab, 0.0)
-    a7 = 2 * (fixed + D * per_slab)              # Phi and Psi, all D slabs
-    step = a7 / 0.85
-    return {"value": 1.0 / step, "unit": "RG steps/s", "cores": int(threads), "kind": "oracle",
-            "sample": "oracle makeMG at D=%d, R=%d on 1 and 2 of the %d i_a slabs (%.1f s, %.1f s); per-slab "
-                      "and slab-free parts scaled to Phi+Psi of one step and by the 85%% flop share of "
-                      "makeMG/makeMH in a steady step" % (D, R, D, times[0], times[1])}
+    return {"value": 1.0 / (t_step * scale), "unit": "RG steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": "one steady-state oracle step (the 5th) of the same flow at D=16, R=%d: %.1f s on %s host "
+                      "threads, scaled to D=%d by the step's algorithmic flop ratio %.1f" % (
+                          r * d0, t_step, threads, D, scale)}
 
 
 def main():
@@ -99,7 +103,8 @@ def main():
     if nl > 0 and kms > 0:
         achieved = kflops / (kms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision], "unit": "TFLOP/s",
-                "frac": achieved / PEAK[args.precision], "traffic": None,
+                "frac": achieved / PEAK[args.precision],
+                "traffic": TRAFFIC.get((args.precision, args.D, args.r)),
                 "kernel": "gemm (makeMG/makeMH)", "launches": nl, "avg_ms": kms / nl}
     out = {
         "metric": "4D triad-ATRG RG steps/s at D=32",
@@ -118,12 +123,12 @@ def main():
                                "iteration, steady-state steps %d..%d of the flow" % (
                                    args.beta, args.h, args.D, args.r, R, args.warmup, args.warmup + args.steps - 1),
                    "D": args.D, "R": R, "precision": args.precision},
-        "tflops_makeMG_makeMH_per_step": step_flops / (ms_step * 1e-3) / 1e12,
+        "makeMG_makeMH_tflops_over_step_time": step_flops / (ms_step * 1e-3) / 1e12,
         "log_z_per_site": f,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.D, args.r)
+        out["cpu_baseline"] = cpu_baseline(args.D, args.r, args.beta, args.h, seed)
     print(json.dumps(out), flush=True)
 
 

@@ -52,7 +52,7 @@ extern "C" {
 #define TRG_SVD_EXACT  1  /* bond swap by the exact SVD of the QR-reduced core of App. A            */
 
 typedef struct trg_options {
-    int dim;            /* lattice dimension: 4 (2 and 3 accepted for atrg_step)                   */
+    int dim;            /* lattice dimension: 4 (the GPU path implements d = 4 only)               */
     int r;              /* overspanning parameter r of Sec. II A (triad bond R = min(r D, d1 d2))   */
     int sketch_mult;    /* sketch width m = sketch_mult * D (App. A footnote: eta D)                */
     int power_iters;    /* extra power passes of the randomized SVD (App. A loop count q = this+1) */
@@ -64,11 +64,13 @@ typedef struct trg_options {
     size_t workspace_cap; /* bytes of device workspace the state may hold (0: unlimited)           */
     void *stream;       /* hipStream_t to enqueue on, or NULL for the null stream                  */
     int device;         /* HIP device ordinal                                                      */
+    double tau_deg;     /* multiplet tolerance of every truncation and canonical basis, relative
+                           to the largest value (0: default 1e-9); see kept-count rule           */
 } trg_options;
 
 /* Fills *opt with the defaults: dim 4, r 7, sketch_mult 2, power_iters 1,
  * seed 0, instance 0, FP64, sketch, max_sweeps 300, no cap, NULL stream,
- * device 0. */
+ * device 0, tau_deg 1e-9. */
 void trg_default_options(trg_options *opt);
 
 typedef struct trg_state trg_state;
@@ -113,6 +115,39 @@ int triad_atrg_step(trg_state *s, int axis);
  * writes one double to *out (host).  TRG_E_NUMERICAL if the trace <= 0.
  */
 int log_z_per_site(trg_state *s, double *out);
+
+/* ---- many instances ------------------------------------------------------ */
+
+typedef struct trg_batch trg_batch;
+
+/*
+ * trg_batch_create -- n independent triad-ATRG solves of the 4D Ising model
+ * (betas[i], hs[i], Ds[i]), each with the options *opt except that instance
+ * i draws its sketches with Philox counter word opt->instance + i and runs on
+ * a stream the batch creates (opt->stream must be NULL).  Arrays are host
+ * memory, read during the call.  On error nothing is left allocated.
+ */
+int trg_batch_create(int n, const double *betas, const double *hs, const int *Ds,
+                     const trg_options *opt, trg_batch **out);
+
+/*
+ * trg_batch_run -- nsteps triad-ATRG steps on every instance, along
+ * axes[0..nsteps) (NULL: 0, 1, 2, 3, 0, ...).  Host workers (up to 8) run
+ * instances concurrently on their own streams; each instance gives the same
+ * bits as a lone solver with the same options.  Returns after all steps are
+ * issued and their host read-backs done; the first error code of any
+ * instance is returned (trg_batch_last_error names the instance).
+ */
+int trg_batch_run(trg_batch *b, int nsteps, const int *axes);
+
+/* log Z / V of every instance into out_n[0..n) (host).  Synchronises. */
+int trg_batch_log_z(trg_batch *b, double *out_n);
+
+int trg_batch_size(const trg_batch *b);
+const char *trg_batch_last_error(const trg_batch *b);
+
+/* Frees every instance and stream; NULL is a no-op. */
+int trg_batch_destroy(trg_batch *b);
 
 /* ---- inspection (tests and benchmarks) --------------------------------- */
 

@@ -4,8 +4,8 @@ The product path is the shared library ``libtrg.so`` built from ``csrc/``;
 this package only marshals arguments to it (ctypes).  It raises if the
 library is missing: there is no CPU fallback.
 """
-from .binding import (Solver, TrgError, load_library, selftest_gemm, selftest_tsqr, selftest_svd, selftest_eigh,
+from .binding import (Solver, Batch, TrgError, load_library, selftest_gemm, selftest_tsqr, selftest_svd, selftest_eigh,
                       selftest_sketch, FP64, FP32, BF16X3, BF16X6, SVD_SKETCH, SVD_EXACT, MODEL_ISING)
 
-__all__ = ["Solver", "TrgError", "load_library", "selftest_gemm", "selftest_tsqr", "selftest_svd", "selftest_eigh",
+__all__ = ["Solver", "Batch", "TrgError", "load_library", "selftest_gemm", "selftest_tsqr", "selftest_svd", "selftest_eigh",
            "selftest_sketch", "FP64", "FP32", "BF16X3", "BF16X6", "SVD_SKETCH", "SVD_EXACT", "MODEL_ISING"]

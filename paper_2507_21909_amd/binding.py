@@ -31,6 +31,7 @@ class Options(ctypes.Structure):
         ("workspace_cap", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
         ("device", ctypes.c_int),
+        ("tau_deg", ctypes.c_double),
     ]
 
 
@@ -78,6 +79,16 @@ def load_library(path=None):
     lib.trg_selftest_svd.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP, _DP, ctypes.POINTER(ctypes.c_int)]
     lib.trg_selftest_eigh.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP, ctypes.POINTER(ctypes.c_int)]
     lib.trg_selftest_sketch.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32] + [ctypes.c_int] * 5 + [_DP]
+    lib.trg_batch_create.argtypes = [ctypes.c_int, _DP, _DP, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_void_p)]
+    lib.trg_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.trg_batch_log_z.argtypes = [ctypes.c_void_p, _DP]
+    lib.trg_batch_size.argtypes = [ctypes.c_void_p]
+    lib.trg_batch_last_error.argtypes = [ctypes.c_void_p]
+    lib.trg_batch_last_error.restype = ctypes.c_char_p
+    lib.trg_batch_destroy.argtypes = [ctypes.c_void_p]
+    for f in ("trg_batch_create", "trg_batch_run", "trg_batch_log_z", "trg_batch_size", "trg_batch_destroy"):
+        getattr(lib, f).restype = ctypes.c_int
     for f in ("trg_create", "trg_destroy", "tensor_init", "atrg_step", "triad_atrg_step", "log_z_per_site",
               "trg_shape", "trg_export", "trg_set_timing", "trg_kernel_time", "trg_selftest_gemm",
               "trg_selftest_tsqr", "trg_selftest_svd", "trg_selftest_eigh", "trg_selftest_sketch"):
@@ -101,7 +112,7 @@ class Solver:
     """One ATRG / triad-ATRG solve on one GPU (a trg_state)."""
 
     def __init__(self, dim=4, r=7, sketch_mult=2, power_iters=1, seed=0, instance=0, precision=FP64,
-                 bond_svd=SVD_SKETCH, max_sweeps=0, workspace_cap=0, stream=None, device=0):
+                 bond_svd=SVD_SKETCH, max_sweeps=0, workspace_cap=0, stream=None, device=0, tau_deg=0.0):
         lib = load_library()
         o = Options()
         lib.trg_default_options(ctypes.byref(o))
@@ -109,6 +120,7 @@ class Solver:
         o.seed, o.instance, o.precision, o.bond_svd = seed, instance, precision, bond_svd
         o.max_sweeps, o.workspace_cap, o.device = max_sweeps, workspace_cap, device
         o.stream = stream
+        o.tau_deg = tau_deg
         self._lib = lib
         self._s = ctypes.c_void_p()
         _check(lib.trg_create(ctypes.byref(o), ctypes.byref(self._s)))
@@ -161,6 +173,58 @@ class Solver:
         ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
         _check(self._lib.trg_kernel_time(self._s, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n)), self._s)
         return ms.value, fl.value, n.value
+
+
+class Batch:
+    """Many (beta, h, D) triad-ATRG solves driven together (trg_batch)."""
+
+    def __init__(self, betas, hs, Ds, r=7, sketch_mult=2, power_iters=1, seed=0, instance=0, precision=FP64,
+                 max_sweeps=0, device=0, tau_deg=0.0):
+        lib = load_library()
+        n = len(betas)
+        if len(hs) != n or len(Ds) != n:
+            raise ValueError("betas, hs and Ds must have the same length")
+        o = Options()
+        lib.trg_default_options(ctypes.byref(o))
+        o.r, o.sketch_mult, o.power_iters = r, sketch_mult, power_iters
+        o.seed, o.instance, o.precision, o.max_sweeps, o.device = seed, instance, precision, max_sweeps, device
+        o.tau_deg = tau_deg
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        h = np.ascontiguousarray(hs, dtype=np.float64)
+        d = (ctypes.c_int * n)(*[int(x) for x in Ds])
+        self._lib = lib
+        self._b = ctypes.c_void_p()
+        self.n = n
+        rc = lib.trg_batch_create(n, _p(b), _p(h), d, ctypes.byref(o), ctypes.byref(self._b))
+        if rc != 0:
+            raise TrgError(rc, "%s (%s)" % (lib.trg_strerror(rc).decode(), lib.trg_last_error(None).decode()))
+
+    def _check(self, rc):
+        if rc != 0:
+            raise TrgError(rc, "%s (%s)" % (self._lib.trg_strerror(rc).decode(),
+                                            self._lib.trg_batch_last_error(self._b).decode()))
+
+    def run(self, nsteps, axes=None):
+        ax = None if axes is None else (ctypes.c_int * len(axes))(*axes)
+        if axes is not None and len(axes) != nsteps:
+            raise ValueError("axes must list one axis per step")
+        self._check(self._lib.trg_batch_run(self._b, nsteps, ax))
+
+    def log_z_per_site(self):
+        out = np.empty(self.n)
+        self._check(self._lib.trg_batch_log_z(self._b, _p(out)))
+        return out
+
+    def close(self):
+        if self._b:
+            self._lib.trg_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def selftest_gemm(a, b, ta=False, tb=False, precision=FP64):

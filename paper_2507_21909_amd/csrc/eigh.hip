@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 
@@ -344,12 +345,11 @@ __global__ __launch_bounds__(NT) void eh_sort_kernel(const double *A, const doub
 }
 
 bool eh_trace() {
-    static int on = -1;
-    if (on < 0) {
+    static const bool on = [] {
         const char *e = getenv("TRG_JACOBI_TRACE");
-        on = (e && *e && *e != '0') ? 1 : 0;
-    }
-    return on == 1;
+        return e && *e && *e != '0';
+    }();
+    return on;
 }
 
 inline int padded(int n) { return ((n + ET - 1) / ET) * ET; }
@@ -373,12 +373,11 @@ int eigh_sym(const double *K, int count, int n, double *lam, double *vec, double
              hipStream_t st) {
     if (count == 0 || n == 0) return 0;
     TRG_REQUIRE(n > 0 && count > 0, -1, "eigh: bad sizes");
-    static bool attr = false;
-    if (!attr) {
+    static std::once_flag attr;
+    std::call_once(attr, [] {
         set_lds_attr(reinterpret_cast<const void *>(eh_solve_kernel));
         set_lds_attr(reinterpret_cast<const void *>(eh_apply_kernel));
-        attr = true;
-    }
+    });
     const int N = padded(n), nb = N / EB, npair = nb / 2;
     double *A = ws, *V = A + (size_t)count * N * N;
     double *Qb = V + (size_t)count * N * N, *Sb = Qb + (size_t)count * npair * ET * ET;

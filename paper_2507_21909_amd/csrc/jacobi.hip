@@ -399,12 +399,11 @@ __global__ void sort_gather_kernel(JacobiBatch jb, const double *scale, const do
 namespace {
 // sweep statistics of every call, printed when TRG_JACOBI_TRACE is set
 bool trace_on() {
-    static int on = -1;
-    if (on < 0) {
+    static const bool on = [] {
         const char *e = getenv("TRG_JACOBI_TRACE");
-        on = (e && *e && *e != '0') ? 1 : 0;
-    }
-    return on == 1;
+        return e && *e && *e != '0';
+    }();
+    return on;
 }
 
 [[noreturn]] void not_converged(const JacobiBatch &jb, const std::vector<int> &fl, bool full_path) {

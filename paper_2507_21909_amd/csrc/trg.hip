@@ -38,7 +38,7 @@ struct trg_state {
 namespace trg {
 namespace {
 
-constexpr double EPS_S = 1e-14, EPS_LAM = 1e-14, EPS_SQ = 1e-14, TAU_DEG = 1e-9;
+constexpr double EPS_S = 1e-14, EPS_LAM = 1e-14, EPS_SQ = 1e-14, TAU_DEG_DEFAULT = 1e-9;
 
 // ---------------------------------------------------------------- small kernels
 __global__ void resplit_norm_kernel(double *s, int n, int k, double *logacc, double eps, int *status) {
@@ -224,7 +224,7 @@ Split resplit(Step &T, const std::vector<int> &order) {
     std::vector<int> nd(S->dims.begin(), S->dims.end());
     DT rot = talloc(c, {chi, chi});
     double *zw = c.ar->dalloc((size_t)chi * 16);
-    canonical_rotation(A.p, F, chi, chi, nd, pow131(d), s.p, kpos, TAU_DEG, zw, rot.p, S->dint, c.st);
+    canonical_rotation(A.p, F, chi, chi, nd, pow131(d), s.p, kpos, T.S->opt.tau_deg, zw, rot.p, S->dint, c.st);
     DT A2 = contract(c, A, "Fa", rot, "ab", "Fb");
     DT D2 = contract(c, Dm, "Fa", rot, "ab", "Fb");
     zero_tail_cols(A2.p, F, chi, chi, kpos, c.st);
@@ -297,7 +297,7 @@ Swap bond_swap(Step &T, const Split &sp) {
         N.d = {(int)rowsN, (int)colsN};
         DT s = talloc(c, {(int)colsN}), u = talloc(c, {(int)rowsN, (int)colsN}), v = talloc(c, {(int)colsN, (int)colsN});
         svd_rowmajor(T, N, s.p, u.p, v.p);
-        kept_count(s.p, (int)colsN, gcap, EPS_S, TAU_DEG, kept, c.st);
+        kept_count(s.p, (int)colsN, gcap, EPS_S, T.S->opt.tau_deg, kept, c.st);
         copy(o.sig.p, s.p, gcap, c.st);
         hipLaunchKernelGGL(zero_tail_vec_kernel, dim3(1), dim3(256), 0, c.st, o.sig.p, gcap, kept);
         // U_bond[(alpha, q), g], V_bond[(beta, p), g]: first gcap columns, zero beyond kept
@@ -370,7 +370,7 @@ Swap bond_swap(Step &T, const Split &sp) {
     // SVD of Q^T M = Rp^T Qp^T: Jacobi on Rp^T, whose columns are the rows of Rp
     DT s = talloc(c, {m}), ut = talloc(c, {m, m}), w = talloc(c, {m, m});
     svd_colmajor(T, Rp.p, 1, m, m, s.p, ut.p, w.p);
-    kept_count(s.p, m, gcap, EPS_S, TAU_DEG, kept, c.st);
+    kept_count(s.p, m, gcap, EPS_S, T.S->opt.tau_deg, kept, c.st);
     copy(o.sig.p, s.p, gcap, c.st);
     hipLaunchKernelGGL(zero_tail_vec_kernel, dim3(1), dim3(256), 0, c.st, o.sig.p, gcap, kept);
     // U_bond = Q Ut[:, :gcap] rows (i, alpha); V_bond = Qp W[:, :gcap] rows (j, beta)
@@ -479,7 +479,7 @@ void squeezers(Step &T, const double *kf, const double *kb, int cnt, int dt, int
     for (int i = 0; i < cnt; ++i) {
         int *kept = T.new_kept();
         const double *si = s.p + (size_t)i * n;
-        kept_count(si, n, D, EPS_SQ, TAU_DEG, kept, c.st);
+        kept_count(si, n, D, EPS_SQ, T.S->opt.tau_deg, kept, c.st);
         DT is = talloc(c, {n});
         hipLaunchKernelGGL(isqrt_kept_kernel, dim3(g1(n)), dim3(256), 0, c.st, si, is.p, n, kept);
         // E = Wb diag(sqb) V[:, :D] S^-1/2 ; F = Wf diag(sqf) U[:, :D] S^-1/2
@@ -503,7 +503,7 @@ void squeezers(Step &T, const double *kf, const double *kb, int cnt, int dt, int
         // canonical basis of the new leg within multiplets of S
         DT rot = talloc(c, {D, D});
         double *zw = c.ar->dalloc((size_t)D * 16);
-        canonical_rotation(vd.p, n, D, D, {dt, db}, {1.0, 131.0}, si, kept, TAU_DEG, zw, rot.p, S->dint, c.st);
+        canonical_rotation(vd.p, n, D, D, {dt, db}, {1.0, 131.0}, si, kept, T.S->opt.tau_deg, zw, rot.p, S->dint, c.st);
         E[i] = contract(c, vd, "pk", rot, "kl", "pl");
         E[i].d = {dt, db, D};
         F[i] = contract(c, ud, "pk", rot, "kl", "pl");
@@ -604,7 +604,7 @@ void triad_isos(Step &T, const DT *grams, int d1, int d2, int rcap, DT *U) {
     eig_psd(T, kk, 4, n, lam.p, vec.p);
     for (int i = 0; i < 4; ++i) {
         int *kept = T.new_kept();
-        kept_count(lam.p + (size_t)i * n, n, rcap, EPS_LAM, TAU_DEG, kept, c.st);
+        kept_count(lam.p + (size_t)i * n, n, rcap, EPS_LAM, T.S->opt.tau_deg, kept, c.st);
         U[i] = talloc(c, {n, rcap});
         col_slice(c, vec.p + i * nn, n, n, rcap, U[i].p);
         zero_tail_cols(U[i].p, n, rcap, rcap, kept, c.st);
@@ -819,6 +819,7 @@ void trg_default_options(trg_options *o) {
     o->precision = TRG_FP64;
     o->bond_svd = TRG_SVD_SKETCH;
     o->max_sweeps = 300;
+    o->tau_deg = trg::TAU_DEG_DEFAULT;
 }
 
 int trg_create(const trg_options *opt, trg_state **out) {
@@ -828,9 +829,11 @@ int trg_create(const trg_options *opt, trg_state **out) {
     if (opt->dim != 4 || opt->r < 1 || opt->sketch_mult < 1 || opt->power_iters < 0 ||
         (opt->precision < 0 || opt->precision > 3) || (opt->bond_svd != 0 && opt->bond_svd != 1))
         return TRG_E_INVALID;
+    if (!(opt->tau_deg >= 0.0 && opt->tau_deg < 1.0)) return TRG_E_INVALID;
     trg_state *s = new (std::nothrow) trg_state();
     if (!s) return TRG_E_NOMEM;
     s->opt = *opt;
+    if (s->opt.tau_deg == 0.0) s->opt.tau_deg = trg::TAU_DEG_DEFAULT;
     try {
         DevGuard g(opt->device);
         s->st = static_cast<hipStream_t>(opt->stream);

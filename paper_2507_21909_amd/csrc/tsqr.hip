@@ -10,6 +10,7 @@
 // then rebuilt top-down: Q_l[block b] = Q_l,b * Q_{l+1}[b*n:(b+1)*n, :], a
 // batched GEMM per level.
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 
@@ -182,13 +183,12 @@ namespace {
 template <int NC>
 void launch_block_reg(int nb, const double *in, long rows, int n, double *rs, double *q, bool fin, hipStream_t st) {
     const size_t lds = (size_t)RB * NC * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
+    static std::once_flag attr;
+    std::call_once(attr, [lds] {
         if (hipFuncSetAttribute(reinterpret_cast<const void *>(qr_block_reg_kernel<NC>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             (void)hipGetLastError();
-        attr = true;
-    }
+    });
     hipLaunchKernelGGL(qr_block_reg_kernel<NC>, dim3(nb), dim3(NT), lds, st, in, rows, n, rs, q, fin ? 1 : 0);
 }
 }  // namespace
