@@ -21,23 +21,43 @@ constexpr int BM = 64, BN = 64, BK = 16, NT = 256, LP = 4;  // LP: LDS row paddi
 
 // TAG only names the instance: 1 for the timed coarse-graining contractions
 // (makeMG / makeMH), so a kernel trace separates them from the other GEMMs.
+// KB: K slab staged per barrier pair (32 measured slower than 16 on the
+// coarse-graining shapes: occupancy falls from 4 to 3 wavefronts per SIMD).
 // TM: tile edge (64 or 128); each wavefront owns a (TM/2)^2 quadrant of
 // (TM/32)^2 MFMA tiles.  128 doubles the flops per byte staged (16 flop/B).
-template <int TAG, int TM>
+// Tile order: workgroups go to the 8 XCDs round-robin by linear id, so the id
+// is first remapped to give each XCD a contiguous eighth of the tiles, which
+// it then walks in groups of GM tile rows (column by column inside a group):
+// the group's A panels and the current B panel stay in that XCD's L2.
+constexpr int GM = 8;
+
+__device__ inline void tile_of(int &mt, int &nt) {
+    const int nx = gridDim.x, ny = gridDim.y, T = nx * ny;
+    const int h = blockIdx.y * nx + blockIdx.x;
+    const int L = (T % 8 == 0) ? (h % 8) * (T / 8) + h / 8 : h;
+    const int in_group = GM * nx, first = (L / in_group) * GM;
+    const int gs = min(ny - first, GM);
+    mt = first + (L % in_group) % gs;
+    nt = (L % in_group) / gs;
+}
+
+template <int TAG, int TM, int KB = 16>
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
     constexpr int NI = TM / 32;            // MFMA tiles per wave and dimension
-    constexpr int EPT = TM * BK / NT;      // elements per thread per operand and K tile
-    constexpr int TPR = BK / EPT;          // threads per row (k-fast loads)
+    constexpr int EPT = TM * KB / NT;      // elements per thread per operand and K tile
+    constexpr int TPR = KB / EPT;          // threads per row (k-fast loads)
     const int bz = blockIdx.z;
     const double *A = g.A + (long)bz * g.sAb;
     const double *B = g.B + (long)bz * g.sBb;
     double *C = g.C + (long)bz * g.sCb;
-    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
+    int mt, nt;
+    tile_of(mt, nt);
+    const int m0 = mt * TM, n0 = nt * TM;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
 
-    __shared__ double As[BK][TM + LP];
-    __shared__ double Bs[BK][TM + LP];
+    __shared__ double As[KB][TM + LP];
+    __shared__ double Bs[KB][TM + LP];
 
     // loader mapping (EPT elements per thread per operand)
     const bool a_kfast = (g.sAk == 1) || (g.sAr != 1);
@@ -70,14 +90,14 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < NI; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-    const int nk = (g.K + BK - 1) / BK;
+    const int nk = (g.K + KB - 1) / KB;
     load(0);
     store();
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
-        if (kt + 1 < nk) load((kt + 1) * BK);
+        if (kt + 1 < nk) load((kt + 1) * KB);
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
+        for (int kk = 0; kk < KB; kk += 4) {
             const int kr = kk + (lane >> 4);
             double af[NI], bf[NI];
 #pragma unroll
