@@ -1,0 +1,127 @@
+// Batched Cholesky factorisation K = L L^T of symmetric positive definite
+// matrices, for the square roots of the squeezer environment Grams (Sec. II A):
+// R = L^T satisfies R^T R = K, and any two square roots of K differ by an
+// orthogonal factor on the left, which cancels in the squeezer pair
+// E = R_b^T V S^-1/2, F = R_f^T U S^-1/2 (U S V^T the SVD of R_f R_b^T).
+//
+// Right-looking, blocks of 64: the diagonal block is factorised in LDS by one
+// workgroup per matrix (which also inverts it), the panel below is multiplied
+// by that inverse (GEMM), and the trailing matrix takes the rank-64 update
+// (GEMM, alpha = -1, beta = 1).  A pivot that is not positive and finite marks
+// the matrix in status[] (the caller then takes the eigen-decomposition route).
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace trg {
+
+namespace {
+constexpr int CB = 64;       // block edge
+constexpr int CT = 256;      // threads per workgroup
+constexpr int CLD = CB + 1;  // LDS row stride
+
+// Factor K[j0:j0+nb, j0:j0+nb] of matrix blockIdx.x in place (lower triangle,
+// upper set to zero); winv <- (L_jj^-1)^T (nb x nb, row-major, stride CB).
+__global__ __launch_bounds__(CT) void chol_diag_kernel(double *K, int n, int j0, int nb, double *winv,
+                                                      int *status) {
+    __shared__ double a[CB * CLD];
+    __shared__ double x[CB * CLD];
+    const int mat = blockIdx.x, t = threadIdx.x;
+    double *Km = K + (size_t)mat * n * n;
+    for (int e = t; e < nb * nb; e += CT) {
+        const int i = e / nb, j = e % nb;
+        a[i * CLD + j] = Km[(size_t)(j0 + i) * n + j0 + j];
+    }
+    __syncthreads();
+    for (int k = 0; k < nb; ++k) {
+        if (t == 0) {
+            double d = a[k * CLD + k];
+            if (!(d > 0.0) || !isfinite(d)) {
+                status[mat] = 1;
+                d = 1.0;
+            }
+            a[k * CLD + k] = sqrt(d);
+        }
+        __syncthreads();
+        const double dk = a[k * CLD + k];
+        for (int i = k + 1 + t; i < nb; i += CT) a[i * CLD + k] /= dk;
+        __syncthreads();
+        const int m = nb - k - 1;
+        for (int e = t; e < m * m; e += CT) {
+            const int i = k + 1 + e / m, j = k + 1 + e % m;
+            if (j <= i) a[i * CLD + j] -= a[i * CLD + k] * a[j * CLD + k];
+        }
+        __syncthreads();
+    }
+    // X = L^-1 by forward substitution, one column per thread
+    if (t < nb) {
+        const int c = t;
+        for (int i = 0; i < nb; ++i) {
+            double s = i == c ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) s -= a[i * CLD + k] * x[k * CLD + c];
+            x[i * CLD + c] = i < c ? 0.0 : s / a[i * CLD + i];
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < nb * nb; e += CT) {
+        const int i = e / nb, j = e % nb;
+        Km[(size_t)(j0 + i) * n + j0 + j] = j <= i ? a[i * CLD + j] : 0.0;
+        winv[(size_t)mat * CB * CB + i * CB + j] = x[j * CLD + i];   // (L^-1)^T
+    }
+}
+
+__global__ void zero_upper_kernel(double *K, int n, int count) {
+    const long tot = (long)count * n * n;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const long rem = e % ((long)n * n);
+        const int i = (int)(rem / n), j = (int)(rem % n);
+        if (j > i) K[e] = 0.0;
+    }
+}
+}  // namespace
+
+size_t chol_ws_doubles(int count, int n) { return (size_t)count * (CB * CB + (size_t)n * CB) + 64; }
+
+bool cholesky_batched(double *K, int count, int n, double *ws, int *status_dev, hipStream_t st) {
+    if (count == 0 || n == 0) return true;
+    TRG_HIP_CHECK(hipMemsetAsync(status_dev, 0, sizeof(int) * count, st));
+    double *winv = ws, *tmp = ws + (size_t)count * CB * CB;
+    for (int j0 = 0; j0 < n; j0 += CB) {
+        const int nb = std::min(CB, n - j0), rows = n - j0 - nb;
+        hipLaunchKernelGGL(chol_diag_kernel, dim3(count), dim3(CT), 0, st, K, n, j0, nb, winv, status_dev);
+        TRG_HIP_CHECK(hipGetLastError());
+        if (rows == 0) break;
+        // panel: L[j0+nb:, j0:j0+nb] = K[j0+nb:, j0:j0+nb] L_jj^-T
+        GemmArgs g{};
+        g.M = rows; g.N = nb; g.K = nb; g.batch = count;
+        g.A = K + (size_t)(j0 + nb) * n + j0; g.sAr = n; g.sAk = 1; g.sAb = (long)n * n;
+        g.B = winv; g.sBk = CB; g.sBn = 1; g.sBb = (long)CB * CB;
+        g.C = tmp; g.sCr = nb; g.sCn = 1; g.sCb = (long)rows * nb;
+        g.alpha = 1.0; g.beta = 0.0;
+        gemm(g, P_FP64, st);
+        for (int m = 0; m < count; ++m)
+            TRG_HIP_CHECK(hipMemcpy2DAsync(K + (size_t)m * n * n + (size_t)(j0 + nb) * n + j0, sizeof(double) * n,
+                                           tmp + (size_t)m * rows * nb, sizeof(double) * nb, sizeof(double) * nb,
+                                           rows, hipMemcpyDeviceToDevice, st));
+        // trailing update: K[j0+nb:, j0+nb:] -= L_panel L_panel^T
+        GemmArgs h{};
+        h.M = rows; h.N = rows; h.K = nb; h.batch = count;
+        h.A = K + (size_t)(j0 + nb) * n + j0; h.sAr = n; h.sAk = 1; h.sAb = (long)n * n;
+        h.B = K + (size_t)(j0 + nb) * n + j0; h.sBk = 1; h.sBn = n; h.sBb = (long)n * n;
+        h.C = K + (size_t)(j0 + nb) * n + j0 + nb; h.sCr = n; h.sCn = 1; h.sCb = (long)n * n;
+        h.alpha = -1.0; h.beta = 1.0;
+        gemm(h, P_FP64, st);
+    }
+    hipLaunchKernelGGL(zero_upper_kernel, dim3(std::min<size_t>(((size_t)count * n * n + 255) / 256, 65536)),
+                       dim3(256), 0, st, K, n, count);
+    TRG_HIP_CHECK(hipGetLastError());
+    std::vector<int> fl(count);
+    TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), status_dev, sizeof(int) * count, hipMemcpyDeviceToHost, st));
+    TRG_HIP_CHECK(hipStreamSynchronize(st));
+    for (int f : fl)
+        if (f) return false;
+    return true;
+}
+
+}  // namespace trg

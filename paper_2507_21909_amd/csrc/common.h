@@ -113,6 +113,11 @@ size_t eigh_ws_doubles(int count, int n);
 size_t eigh_iws_ints(int count, int n);
 int eigh_sym(const double *K, int count, int n, double *lam, double *vec, double *ws, int *iws, int max_sweeps,
              hipStream_t st);
+// Batched Cholesky K = L L^T in place (lower, upper zeroed) of `count` n x n
+// matrices; ws: chol_ws_doubles entries; status_dev: count ints.  Returns
+// false (after synchronising) if any pivot was not positive and finite.
+size_t chol_ws_doubles(int count, int n);
+bool cholesky_batched(double *K, int count, int n, double *ws, int *status_dev, hipStream_t st);
 void jacobi_finish(const JacobiBatch &jb, double *s, double *u_sorted, double *v_sorted,
                    double *work, hipStream_t st);
 

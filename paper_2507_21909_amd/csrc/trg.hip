@@ -446,30 +446,40 @@ void squeezers(Step &T, const double *kf, const double *kb, int cnt, int dt, int
     Ctx &c = T.c;
     const int n = dt * db, D = S->D;
     const size_t nn = (size_t)n * n;
-    // eigen-decompositions of all K_f, K_b in one batch: [f0, b0, f1, b1, ...]
+    // square-root factors X (K = X X^T) of all K_f, K_b in one batch, [f0, b0, f1, b1, ...]:
+    // R = X^T.  Cholesky when every Gram is positive definite; otherwise
+    // X = W Lambda^{1/2} from the eigen-decomposition with eigenvalues at or
+    // below EPS_LAM of the largest set to zero.  Any two square roots of K
+    // differ by an orthogonal factor, which cancels in E and F below.
     double *kk = c.ar->dalloc(2 * cnt * nn);
     for (int i = 0; i < cnt; ++i) {
         copy(kk + (2 * i) * nn, kf + i * nn, nn, c.st);
         copy(kk + (2 * i + 1) * nn, kb + i * nn, nn, c.st);
     }
-    DT lam = talloc(c, {2 * cnt, n}), vec = talloc(c, {2 * cnt, n, n}), sq = talloc(c, {2 * cnt, n});
-    eig_psd(T, kk, 2 * cnt, n, lam.p, vec.p);
-    for (int i = 0; i < 2 * cnt; ++i)
-        hipLaunchKernelGGL(sqrt_clamp_kernel, dim3(g1(n)), dim3(256), 0, c.st, lam.p + (size_t)i * n, sq.p + (size_t)i * n,
-                           n, EPS_LAM);
-    // R_f R_b^T = diag(sqf) Wf^T Wb diag(sqb), all cnt in one batch
+    double *xs = c.ar->dalloc(2 * cnt * nn);
+    copy(xs, kk, 2 * cnt * nn, c.st);
+    int *cst = reinterpret_cast<int *>(c.ar->dalloc(cnt + 1));
+    double *cws = c.ar->dalloc(chol_ws_doubles(2 * cnt, n));
+    if (!cholesky_batched(xs, 2 * cnt, n, cws, cst, c.st)) {
+        DT lam = talloc(c, {2 * cnt, n}), sq = talloc(c, {2 * cnt, n});
+        eig_psd(T, kk, 2 * cnt, n, lam.p, xs);
+        for (int i = 0; i < 2 * cnt; ++i) {
+            hipLaunchKernelGGL(sqrt_clamp_kernel, dim3(g1(n)), dim3(256), 0, c.st, lam.p + (size_t)i * n,
+                               sq.p + (size_t)i * n, n, EPS_LAM);
+            DT xi{xs + i * nn, {n, n}};
+            scale_axis(xi.p, xi.d, 1, sq.p + (size_t)i * n, 1, c.st);
+        }
+    }
+    // R_f R_b^T = X_f^T X_b, all cnt in one batch
     DT gm = talloc(c, {cnt, n, n});
     for (int i = 0; i < cnt; ++i) {
         GemmArgs ga{};
         ga.M = n; ga.N = n; ga.K = n; ga.batch = 1;
-        ga.A = vec.p + (2 * i) * nn; ga.sAr = 1; ga.sAk = n;           // Wf^T
-        ga.B = vec.p + (2 * i + 1) * nn; ga.sBk = n; ga.sBn = 1;       // Wb
+        ga.A = xs + (2 * i) * nn; ga.sAr = 1; ga.sAk = n;           // X_f^T
+        ga.B = xs + (2 * i + 1) * nn; ga.sBk = n; ga.sBn = 1;       // X_b
         ga.C = gm.p + i * nn; ga.sCr = n; ga.sCn = 1;
         ga.alpha = 1.0;
         gemm(ga, P_FP64, c.st);
-        DT gi{gm.p + i * nn, {n, n}};
-        scale_axis(gi.p, gi.d, 0, sq.p + (size_t)(2 * i) * n, 1, c.st);
-        scale_axis(gi.p, gi.d, 1, sq.p + (size_t)(2 * i + 1) * n, 1, c.st);
     }
     // SVDs (Jacobi wants column-major: transpose each)
     DT gt = talloc(c, {cnt, n, n});
@@ -482,21 +492,16 @@ void squeezers(Step &T, const double *kf, const double *kb, int cnt, int dt, int
         kept_count(si, n, D, EPS_SQ, T.S->opt.tau_deg, kept, c.st);
         DT is = talloc(c, {n});
         hipLaunchKernelGGL(isqrt_kept_kernel, dim3(g1(n)), dim3(256), 0, c.st, si, is.p, n, kept);
-        // E = Wb diag(sqb) V[:, :D] S^-1/2 ; F = Wf diag(sqf) U[:, :D] S^-1/2
+        // E = X_b V[:, :D] S^-1/2 ; F = X_f U[:, :D] S^-1/2
         DT vd = talloc(c, {n, D}), ud = talloc(c, {n, D});
-        DT vs = talloc(c, {n, n}), us = talloc(c, {n, n});
-        copy(vs.p, v.p + i * nn, nn, c.st);
-        scale_axis(vs.p, vs.d, 0, sq.p + (size_t)(2 * i + 1) * n, 1, c.st);
-        copy(us.p, u.p + i * nn, nn, c.st);
-        scale_axis(us.p, us.d, 0, sq.p + (size_t)(2 * i) * n, 1, c.st);
         GemmArgs ga{};
         ga.M = n; ga.N = D; ga.K = n; ga.batch = 1;
-        ga.A = vec.p + (2 * i + 1) * nn; ga.sAr = n; ga.sAk = 1;
-        ga.B = vs.p; ga.sBk = n; ga.sBn = 1;
+        ga.A = xs + (2 * i + 1) * nn; ga.sAr = n; ga.sAk = 1;
+        ga.B = v.p + i * nn; ga.sBk = n; ga.sBn = 1;
         ga.C = vd.p; ga.sCr = D; ga.sCn = 1;
         ga.alpha = 1.0;
         gemm(ga, P_FP64, c.st);
-        ga.A = vec.p + (2 * i) * nn; ga.B = us.p; ga.C = ud.p;
+        ga.A = xs + (2 * i) * nn; ga.B = u.p + i * nn; ga.C = ud.p;
         gemm(ga, P_FP64, c.st);
         scale_axis(vd.p, vd.d, 1, is.p, 1, c.st);
         scale_axis(ud.p, ud.d, 1, is.p, 1, c.st);
