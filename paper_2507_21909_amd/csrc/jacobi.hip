@@ -58,11 +58,13 @@ __device__ int rotate_pair(double *u, double *v, int m, int n, int mm, int r, in
         up[i] = c * x - s * y;
         uq[i] = s * x + c * y;
     }
-    double *vp = v + (long)p * n, *vq = v + (long)q * n;
-    for (int i = lane; i < n; i += 64) {
-        double x = vp[i], y = vq[i];
-        vp[i] = c * x - s * y;
-        vq[i] = s * x + c * y;
+    if (v) {
+        double *vp = v + (long)p * n, *vq = v + (long)q * n;
+        for (int i = lane; i < n; i += 64) {
+            double x = vp[i], y = vq[i];
+            vp[i] = c * x - s * y;
+            vq[i] = s * x + c * y;
+        }
     }
     return 1;
 }
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(NT) void round_kernel(JacobiBatch jb, int r, double
     const int mm = jb.n + (jb.n & 1);
     if (k >= mm / 2) return;
     double *u = jb.ut + (long)mat * jb.strideU;
-    double *v = jb.vt + (long)mat * jb.strideV;
+    double *v = jb.vt ? jb.vt + (long)mat * jb.strideV : nullptr;
     const int rc = rotate_pair(u, v, jb.m, jb.n, mm, r, k, tol);
     if ((threadIdx.x & 63) == 0) {
         if (rc == 1) atomicAdd(&flags[mat], 1);
@@ -85,7 +87,7 @@ __global__ __launch_bounds__(NT) void round_kernel(JacobiBatch jb, int r, double
 __global__ __launch_bounds__(NT) void full_kernel(JacobiBatch jb, int max_sweeps, double tol, int *flags) {
     const int mat = blockIdx.x;
     double *u = jb.ut + (long)mat * jb.strideU;
-    double *v = jb.vt + (long)mat * jb.strideV;
+    double *v = jb.vt ? jb.vt + (long)mat * jb.strideV : nullptr;
     const int mm = jb.n + (jb.n & 1);
     const int w = threadIdx.x >> 6;
     __shared__ int rot, bad;
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r
     const int k = blockIdx.x, mat = blockIdx.y, t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int I = player_at(nb, k, r), J = player_at(nb, nb - 1 - k, r);
     double *U = jb.ut + (long)mat * jb.strideU;
-    double *V = jb.vt + (long)mat * jb.strideV;
+    double *V = jb.vt ? jb.vt + (long)mat * jb.strideV : nullptr;
     const int m = jb.m, n = jb.n;
     __shared__ double red[NT / 64][24];
     __shared__ double rc[8], rs[8];
@@ -293,6 +295,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r
         for (int c = 0; c < PW; ++c) vpan[t][c] = vrow[c];
     }
     __syncthreads();
+    if (!V) return;
     // V[:, panel] <- V[:, panel] * (panel rotation); thread t holds rows t + 256 j
     // (n <= m, so ROWS covers them); each thread reads its rows before writing them
     double vv[PW][ROWS];
@@ -385,14 +388,16 @@ __global__ void sort_gather_kernel(JacobiBatch jb, const double *scale, const do
     const int rk = rank_sh;
     if (threadIdx.x == 0) s[(long)mat * jb.n + rk] = sj * scale[mat];
     const double *u = jb.ut + (long)mat * jb.strideU + (long)j * jb.m;
-    const double *v = jb.vt + (long)mat * jb.strideV + (long)j * jb.n;
     double inv = sj > 0.0 ? 1.0 / sj : 0.0;
     if (us) {
         double *uo = us + (long)mat * jb.m * jb.n;
         for (int i = threadIdx.x; i < jb.m; i += blockDim.x) uo[(long)i * jb.n + rk] = u[i] * inv;
     }
-    double *vo = vs + (long)mat * jb.n * jb.n;
-    for (int i = threadIdx.x; i < jb.n; i += blockDim.x) vo[(long)i * jb.n + rk] = v[i];
+    if (vs && jb.vt) {
+        const double *v = jb.vt + (long)mat * jb.strideV + (long)j * jb.n;
+        double *vo = vs + (long)mat * jb.n * jb.n;
+        for (int i = threadIdx.x; i < jb.n; i += blockDim.x) vo[(long)i * jb.n + rk] = v[i];
+    }
 }
 }  // namespace
 
@@ -428,7 +433,8 @@ int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *wo
     if (jb.count == 0 || jb.n == 0) return 0;
     const double tol = sqrt((double)jb.m) * 2.220446049250313e-16;
     hipLaunchKernelGGL(scale_kernel, dim3(jb.count), dim3(NT), 0, st, jb, work);
-    hipLaunchKernelGGL(init_v_kernel, dim3(cdiv((size_t)jb.count * jb.n * jb.n, 256)), dim3(256), 0, st, jb);
+    if (jb.vt)
+        hipLaunchKernelGGL(init_v_kernel, dim3(cdiv((size_t)jb.count * jb.n * jb.n, 256)), dim3(256), 0, st, jb);
     TRG_HIP_CHECK(hipGetLastError());
     const int mm = jb.n + (jb.n & 1);
     std::vector<int> fl(2 * jb.count);

@@ -167,7 +167,7 @@ void svd_colmajor(Step &T, const double *a, int count, int m, int n, double *s, 
     Ctx &c = T.c;
     double *ut = c.ar->dalloc((size_t)count * m * n);
     copy(ut, a, (size_t)count * m * n, c.st);
-    double *vt = c.ar->dalloc((size_t)count * n * n);
+    double *vt = v ? c.ar->dalloc((size_t)count * n * n) : nullptr;   // no V wanted: not accumulated
     double *work = c.ar->dalloc((size_t)count * (n + 1));
     int *flags = reinterpret_cast<int *>(c.ar->dalloc((size_t)count));   // 2 * count ints
     JacobiBatch jb{count, m, n, ut, vt, (long)m * n, (long)n * n};
@@ -484,24 +484,35 @@ void squeezers(Step &T, const double *kf, const double *kb, int cnt, int dt, int
     // SVDs (Jacobi wants column-major: transpose each)
     DT gt = talloc(c, {cnt, n, n});
     permute(gm.p, gt.p, {cnt, n, n}, {0, 2, 1}, c.st);
-    DT s = talloc(c, {cnt, n}), u = talloc(c, {cnt, n, n}), v = talloc(c, {cnt, n, n});
-    svd_colmajor(T, gt.p, cnt, n, n, s.p, u.p, v.p);
+    // only U is accumulated: the kept right vectors follow as V_D = M^T U_D S^-1
+    DT s = talloc(c, {cnt, n}), u = talloc(c, {cnt, n, n});
+    svd_colmajor(T, gt.p, cnt, n, n, s.p, u.p, nullptr);
     for (int i = 0; i < cnt; ++i) {
         int *kept = T.new_kept();
         const double *si = s.p + (size_t)i * n;
         kept_count(si, n, D, EPS_SQ, T.S->opt.tau_deg, kept, c.st);
         DT is = talloc(c, {n});
         hipLaunchKernelGGL(isqrt_kept_kernel, dim3(g1(n)), dim3(256), 0, c.st, si, is.p, n, kept);
+        DT v0 = talloc(c, {n, D});
+        GemmArgs gv{};
+        gv.M = n; gv.N = D; gv.K = n; gv.batch = 1;
+        gv.A = gm.p + i * nn; gv.sAr = 1; gv.sAk = n;                  // M^T
+        gv.B = u.p + i * nn; gv.sBk = n; gv.sBn = 1;                   // U[:, :D]
+        gv.C = v0.p; gv.sCr = D; gv.sCn = 1;
+        gv.alpha = 1.0;
+        gemm(gv, P_FP64, c.st);
+        scale_axis(v0.p, v0.d, 1, is.p, 1, c.st);
+        scale_axis(v0.p, v0.d, 1, is.p, 1, c.st);                      // * S^-1 (0 past the kept ones)
         // E = X_b V[:, :D] S^-1/2 ; F = X_f U[:, :D] S^-1/2
         DT vd = talloc(c, {n, D}), ud = talloc(c, {n, D});
         GemmArgs ga{};
         ga.M = n; ga.N = D; ga.K = n; ga.batch = 1;
         ga.A = xs + (2 * i + 1) * nn; ga.sAr = n; ga.sAk = 1;
-        ga.B = v.p + i * nn; ga.sBk = n; ga.sBn = 1;
+        ga.B = v0.p; ga.sBk = D; ga.sBn = 1;
         ga.C = vd.p; ga.sCr = D; ga.sCn = 1;
         ga.alpha = 1.0;
         gemm(ga, P_FP64, c.st);
-        ga.A = xs + (2 * i) * nn; ga.B = u.p + i * nn; ga.C = ud.p;
+        ga.A = xs + (2 * i) * nn; ga.B = u.p + i * nn; ga.sBk = n; ga.C = ud.p;
         gemm(ga, P_FP64, c.st);
         scale_axis(vd.p, vd.d, 1, is.p, 1, c.st);
         scale_axis(ud.p, ud.d, 1, is.p, 1, c.st);
