@@ -34,12 +34,15 @@ enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16X3 = 2, P_BF16X6 = 3 };
 
 // ---- GEMM: C[b] = alpha * sum_k A[b](r,k) B[b](k,n) + beta * C[b] -----------------
 // Element (r, k) of A[b] is at A + b*sAb + r*sAr + k*sAk (likewise B, C).
+// With inner > 1 the batch is two-level: z = outer * inner + i, outer < batch,
+// and operand offsets add i * sAi (sBi, sCi) to outer * sAb (sBb, sCb) (split K).
 struct GemmArgs {
     int M, N, K, batch;
     const double *A; long sAr, sAk, sAb;
     const double *B; long sBk, sBn, sBb;
     double *C; long sCr, sCn, sCb;
     double alpha, beta;
+    int inner; long sAi, sBi, sCi;
 };
 // ev0 / ev1 (optional): events stamped at the kernel's start and end
 void gemm(const GemmArgs &g, Prec prec, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

@@ -226,7 +226,7 @@ void timed_gemm(Ctx &c, const GemmArgs &g, Prec prec) {
     TRG_HIP_CHECK(hipEventCreate(&t.a));
     TRG_HIP_CHECK(hipEventCreate(&t.b));
     gemm(g, prec, c.st, t.a, t.b);   // the launch stamps both events (kernel start, end)
-    t.flops = 2.0 * g.M * (double)g.N * g.K * g.batch;
+    t.flops = 2.0 * g.M * (double)g.N * g.K * g.batch * std::max(1, g.inner);
     c.timed.push_back(t);
 }
 

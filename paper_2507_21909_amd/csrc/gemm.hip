@@ -19,6 +19,16 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 namespace {
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256, LP = 4;  // LP: LDS row padding
 
+// operand pointers of batch entry blockIdx.z (two-level when g.inner > 1)
+__device__ inline void batch_ptrs(const GemmArgs &g, const double *&A, const double *&B, double *&C) {
+    const int bz = blockIdx.z;
+    const int bo = g.inner > 1 ? bz / g.inner : bz, bi = g.inner > 1 ? bz % g.inner : 0;
+    A = g.A + (long)bo * g.sAb + (long)bi * g.sAi;
+    B = g.B + (long)bo * g.sBb + (long)bi * g.sBi;
+    C = g.C + (long)bo * g.sCb + (long)bi * g.sCi;
+}
+
+
 // TAG only names the instance: 1 for the timed coarse-graining contractions
 // (makeMG / makeMH), so a kernel trace separates them from the other GEMMs.
 // KB: K slab staged per barrier pair (32 measured slower than 16 on the
@@ -46,10 +56,9 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
     constexpr int NI = TM / 32;            // MFMA tiles per wave and dimension
     constexpr int EPT = TM * KB / NT;      // elements per thread per operand and K tile
     constexpr int TPR = KB / EPT;          // threads per row (k-fast loads)
-    const int bz = blockIdx.z;
-    const double *A = g.A + (long)bz * g.sAb;
-    const double *B = g.B + (long)bz * g.sBb;
-    double *C = g.C + (long)bz * g.sCb;
+    const double *A, *B;
+    double *C;
+    batch_ptrs(g, A, B, C);
     int mt, nt;
     tile_of(mt, nt);
     const int m0 = mt * TM, n0 = nt * TM;
@@ -138,9 +147,11 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
 
 void gemm_f64(const GemmArgs &g, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
-    for (int b0 = 0; b0 < g.batch; b0 += 65535) {
+    const int inner = std::max(1, g.inner);
+    TRG_REQUIRE(inner == 1 || (long)g.batch * inner <= 65535, -6, "gemm: two-level batch too large");
+    for (int b0 = 0; b0 < g.batch; b0 += 65535 / inner) {
         GemmArgs h = g;
-        h.batch = std::min(65535, g.batch - b0);
+        h.batch = std::min(65535 / inner, g.batch - b0);
         h.A += (long)b0 * g.sAb;
         h.B += (long)b0 * g.sBb;
         h.C += (long)b0 * g.sCb;
@@ -150,8 +161,8 @@ void gemm_f64(const GemmArgs &g, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
         const bool big = kBigTiles && h.M >= 256 && h.N >= 256 &&
                          (long)cdiv(h.N, 128) * cdiv(h.M, 128) * h.batch >= 256;
         const int tm = big ? 128 : 64;
-        dim3 grid(cdiv(h.N, tm), cdiv(h.M, tm), h.batch);
-        if (ev0 && g.batch <= 65535) {   // kernel start / end timestamps
+        dim3 grid(cdiv(h.N, tm), cdiv(h.M, tm), h.batch * inner);
+        if (ev0 && (long)g.batch * inner <= 65535) {   // kernel start / end timestamps
             if (big) hipExtLaunchKernelGGL(gemm_f64_kernel<1, 128>, grid, dim3(NT), 0, st, ev0, ev1, 0, h);
             else hipExtLaunchKernelGGL(gemm_f64_kernel<1, 64>, grid, dim3(NT), 0, st, ev0, ev1, 0, h);
         } else {
@@ -184,10 +195,9 @@ constexpr int FLUSH_K = 16;   // FP32 partial sums span one K tile at most
 
 // FP32 path: same tiling as the FP64 kernel (BK 16), LDS in FP32
 __global__ __launch_bounds__(NT) void gemm_f32_kernel(GemmArgs g) {
-    const int bz = blockIdx.z;
-    const double *A = g.A + (long)bz * g.sAb;
-    const double *B = g.B + (long)bz * g.sBb;
-    double *C = g.C + (long)bz * g.sCb;
+    const double *A, *B;
+    double *C;
+    batch_ptrs(g, A, B, C);
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
@@ -277,10 +287,9 @@ constexpr int BKB = 32, KP = 8;   // KP: padding in bf16 elements
 
 template <int NSPLIT, int NPROD>
 __global__ __launch_bounds__(NT) void gemm_bf16_kernel(GemmArgs g) {
-    const int bz = blockIdx.z;
-    const double *A = g.A + (long)bz * g.sAb;
-    const double *B = g.B + (long)bz * g.sBb;
-    double *C = g.C + (long)bz * g.sCb;
+    const double *A, *B;
+    double *C;
+    batch_ptrs(g, A, B, C);
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
@@ -392,14 +401,16 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(GemmArgs g) {
 template <typename K>
 void launch_batched(K kern, const GemmArgs &g, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
-    for (int b0 = 0; b0 < g.batch; b0 += 65535) {
+    const int inner = std::max(1, g.inner);
+    TRG_REQUIRE(inner == 1 || (long)g.batch * inner <= 65535, -6, "gemm: two-level batch too large");
+    for (int b0 = 0; b0 < g.batch; b0 += 65535 / inner) {
         GemmArgs h = g;
-        h.batch = std::min(65535, g.batch - b0);
+        h.batch = std::min(65535 / inner, g.batch - b0);
         h.A += (long)b0 * g.sAb;
         h.B += (long)b0 * g.sBb;
         h.C += (long)b0 * g.sCb;
-        dim3 grid(cdiv(h.N, BN), cdiv(h.M, BM), h.batch);
-        if (ev0 && g.batch <= 65535)
+        dim3 grid(cdiv(h.N, BN), cdiv(h.M, BM), h.batch * inner);
+        if (ev0 && (long)g.batch * inner <= 65535)
             hipExtLaunchKernelGGL(kern, grid, dim3(NT), 0, st, ev0, ev1, 0, h);
         else
             hipLaunchKernelGGL(kern, grid, dim3(NT), 0, st, h);

@@ -650,6 +650,10 @@ DT coarse_half(Step &T, const DT &em, const DT &fp, const DT &t23) {
     Arena::Mark mk = c.ar->mark();
     DT z = talloc(c, {xs, U, C, V, G});
     DT zp = talloc(c, {xs, U, V, C, G});
+    const long tiles2 = (long)((Kk * Ll + 63) / 64) * ((C * G + 63) / 64) * xs;
+    int ks = 1;
+    while (ks < 8 && tiles2 * ks < 1024 && (U * V) % (2 * ks) == 0 && (U * V) / (2 * ks) >= 2048) ks *= 2;
+    double *kws = ks > 1 ? c.ar->dalloc((size_t)xs * ks * Kk * Ll * C * G) : nullptr;
     for (int x0 = 0; x0 < X; x0 += xs) {
         const int nx = std::min(xs, X - x0);
         GemmArgs g{};
@@ -662,13 +666,26 @@ DT coarse_half(Step &T, const DT &em, const DT &fp, const DT &t23) {
         z.d[0] = nx;
         zp.d[0] = nx;
         permute(z.p, zp.p, z.d, {0, 1, 3, 2, 4}, c.st);
+        // K2 has few output tiles (D^2 x D^2 per slab) over a long K = R^2: split K
+        // so the launch fills the CUs, then add the slices in a fixed order
+        const long mn = (long)Kk * Ll * C * G;
         GemmArgs h{};
         h.M = Kk * Ll; h.N = C * G; h.K = U * V; h.batch = nx;
         h.A = t23.p; h.sAr = 1; h.sAk = (long)Kk * Ll; h.sAb = 0;
         h.B = zp.p; h.sBk = (long)C * G; h.sBn = 1; h.sBb = zslab;
-        h.C = out.p + (long)x0 * Kk * Ll * C * G; h.sCr = (long)C * G; h.sCn = 1; h.sCb = (long)Kk * Ll * C * G;
         h.alpha = 1.0; h.beta = 0.0;
-        timed_gemm(c, h, c.prec);
+        if (ks > 1) {
+            h.K = U * V / ks;
+            h.inner = ks; h.sAi = (long)h.K * h.sAk; h.sBi = (long)h.K * h.sBk;
+            h.C = kws; h.sCr = (long)C * G; h.sCn = 1; h.sCb = ks * mn; h.sCi = mn;
+            timed_gemm(c, h, c.prec);
+            for (int x = 0; x < nx; ++x)
+                sum_slices(kws + (long)x * ks * mn, ks, (long)Kk * Ll, (long)C * G, out.p + (long)(x0 + x) * mn,
+                           (long)C * G, 1, c.st);
+        } else {
+            h.C = out.p + (long)x0 * mn; h.sCr = (long)C * G; h.sCn = 1; h.sCb = mn;
+            timed_gemm(c, h, c.prec);
+        }
     }
     c.ar->release(mk);
     return out;
