@@ -191,25 +191,20 @@ DT contract(Ctx &c, const DT &a, const std::string &la, const DT &b, const std::
     const long tiles = ((M + 63) / 64) * ((N + 63) / 64) * nb;
     if (K == 0) {
         fill(tgt.p, (size_t)tgt.n(), 0.0, c.st);
-    } else if (nb == 1 && tiles < 128 && K >= 8192) {
-        // split K: few output tiles over a long contraction would run on a handful of CUs
-        const long splits = std::min<long>(K / 2048, (512 + tiles - 1) / tiles);
-        const long chunk = (K + splits - 1) / splits, full = K / chunk, tail = K - full * chunk;
-        const long slices = full + (tail > 0);
-        double *w = c.ar->dalloc((size_t)slices * M * N);
+    } else if (tiles < 512 && K >= 8192 && K % 2048 == 0) {
+        // split K: few output tiles over a long contraction would leave most CUs
+        // idle; the slices are added in a fixed order afterwards
+        long splits = 1;
+        while (splits < 1024 && tiles * splits < 1024 && K % (2 * splits * 1024) == 0 && nb * splits * 2 <= 65535)
+            splits *= 2;
+        double *w = c.ar->dalloc((size_t)nb * splits * M * N);
         GemmArgs h = g;
-        h.K = (int)chunk; h.batch = (int)full;
-        h.sAb = chunk * sAk; h.sBb = chunk * sBk;
-        h.C = w; h.sCr = N; h.sCn = 1; h.sCb = M * N;
+        h.K = (int)(K / splits);
+        h.inner = (int)splits; h.sAi = h.K * sAk; h.sBi = h.K * sBk;
+        h.C = w; h.sCr = N; h.sCn = 1; h.sCb = splits * M * N; h.sCi = M * N;
         gemm(h, prec, c.st);
-        if (tail > 0) {
-            GemmArgs u = h;
-            u.K = (int)tail; u.batch = 1;
-            u.A = g.A + full * chunk * sAk; u.B = g.B + full * chunk * sBk;
-            u.C = w + full * M * N;
-            gemm(u, prec, c.st);
-        }
-        sum_slices(w, (int)slices, M, N, tgt.p, sCr, sCn, c.st);
+        for (long b = 0; b < nb; ++b)
+            sum_slices(w + b * splits * M * N, (int)splits, M, N, tgt.p + b * sCb, sCr, sCn, c.st);
     } else {
         gemm(g, prec, c.st);
     }

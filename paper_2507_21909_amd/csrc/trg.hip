@@ -333,14 +333,16 @@ Swap bond_swap(Step &T, const Split &sp) {
     DT cur = om;
     for (int it = 0; it <= S->opt.power_iters; ++it) {
         // Y[i, alpha, m] = sum_{x, beta} C[x, i, beta] sum_j B[x, j, alpha] Omega[j, beta, m]
+        // t1[(x, alpha), (beta, m)] = sum_j Bp[j, (x, alpha)] Omega[j, (beta, m)]: one GEMM
+        // with rows (x, alpha) contiguous in Bp
         DT t1;
         {
             t1 = talloc(c, {x, chi, chi, m});
             GemmArgs g{};
-            g.M = chi; g.N = chi * m; g.K = (int)J; g.batch = x;
-            g.A = Bt.p; g.sAr = 1; g.sAk = chi; g.sAb = J * chi;
-            g.B = cur.p; g.sBk = (long)chi * m; g.sBn = 1; g.sBb = 0;
-            g.C = t1.p; g.sCr = (long)chi * m; g.sCn = 1; g.sCb = (long)chi * chi * m;
+            g.M = x * chi; g.N = chi * m; g.K = (int)J; g.batch = 1;
+            g.A = Bp.p; g.sAr = 1; g.sAk = (long)x * chi;
+            g.B = cur.p; g.sBk = (long)chi * m; g.sBn = 1;
+            g.C = t1.p; g.sCr = (long)chi * m; g.sCn = 1;
             g.alpha = 1.0; g.beta = 0.0;
             gemm(g, P_FP64, c.st);
         }
@@ -353,10 +355,10 @@ Swap bond_swap(Step &T, const Split &sp) {
         {
             t2 = talloc(c, {x, chi, chi, m});
             GemmArgs g{};
-            g.M = chi; g.N = chi * m; g.K = (int)I; g.batch = x;
-            g.A = Ct.p; g.sAr = 1; g.sAk = chi; g.sAb = I * chi;
-            g.B = Q.p; g.sBk = (long)chi * m; g.sBn = 1; g.sBb = 0;
-            g.C = t2.p; g.sCr = (long)chi * m; g.sCn = 1; g.sCb = (long)chi * chi * m;
+            g.M = x * chi; g.N = chi * m; g.K = (int)I; g.batch = 1;
+            g.A = Cp.p; g.sAr = 1; g.sAk = (long)x * chi;
+            g.B = Q.p; g.sBk = (long)chi * m; g.sBn = 1;
+            g.C = t2.p; g.sCr = (long)chi * m; g.sCn = 1;
             g.alpha = 1.0; g.beta = 0.0;
             gemm(g, P_FP64, c.st);
         }
