@@ -131,14 +131,44 @@ __global__ __launch_bounds__(NT) void eh_solve_kernel(const double *A, int N, in
             }
             __syncthreads();
             if (any_round) {
-                // S <- J^T S J on 2 x 2 blocks (u <= v); the mirror block is the transpose
-                for (int e = t; e < EB * EB; e += NT) {
-                    const int u = e / EB, v = e % EB;
-                    if (u > v) continue;
-                    const int pu = pp[u], qu = qq[u], pv = pp[v], qv = qq[v];
+                // S <- J^T S J on 2 x 2 blocks (u <= v); the mirror block is the transpose.
+                // Thread t always takes column pair v = t % 32 with row pairs u = t / 32 + 8 i,
+                // and in the Q update pair t % 32 on rows t / 32 + 8 i.  All LDS reads of a
+                // phase are issued before its writes, so their latencies overlap.
+                const int vv = t % EB;
+                const int pv = pp[vv], qv = qq[vv];
+                const double cv = cc[vv], sv = ss[vv];
+                double m00[4], m01[4], m10[4], m11[4];
+                int pu[4], qu[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int u = t / EB + 8 * i;
+                    pu[i] = pp[u];
+                    qu[i] = qq[u];
+                    if (u <= vv) {
+                        m00[i] = S[pu[i] * LDT + pv];
+                        m01[i] = S[pu[i] * LDT + qv];
+                        m10[i] = S[qu[i] * LDT + pv];
+                        m11[i] = S[qu[i] * LDT + qv];
+                    }
+                }
+                double qx[8], qy[8];
+                const bool qrot = cv != 1.0 || sv != 0.0;
+                if (qrot) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int i = t / EB + 8 * k;
+                        qx[k] = Q[i * LDT + pv];
+                        qy[k] = Q[i * LDT + qv];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int u = t / EB + 8 * i;
+                    if (u > vv) continue;
                     double n00, n01, n10, n11;
-                    if (u == v) {
-                        const double app = S[pu * LDT + pu], aqq = S[qu * LDT + qu], apq = S[pu * LDT + qu];
+                    if (u == vv) {
+                        const double app = m00[i], aqq = m11[i], apq = m01[i];
                         const double tn = tt[u];
                         if (tn != 0.0) {
                             n00 = app - tn * apq;
@@ -149,40 +179,38 @@ __global__ __launch_bounds__(NT) void eh_solve_kernel(const double *A, int N, in
                             n11 = aqq;
                             n01 = n10 = apq;
                         }
-                        S[pu * LDT + pu] = n00;
-                        S[qu * LDT + qu] = n11;
-                        S[pu * LDT + qu] = n01;
-                        S[qu * LDT + pu] = n10;
+                        S[pu[i] * LDT + pu[i]] = n00;
+                        S[qu[i] * LDT + qu[i]] = n11;
+                        S[pu[i] * LDT + qu[i]] = n01;
+                        S[qu[i] * LDT + pu[i]] = n10;
                         continue;
                     }
-                    const double cu = cc[u], su = ss[u], cv = cc[v], sv = ss[v];
-                    const double m00 = S[pu * LDT + pv], m01 = S[pu * LDT + qv];
-                    const double m10 = S[qu * LDT + pv], m11 = S[qu * LDT + qv];
+                    const double cu = cc[u], su = ss[u];
                     // columns (pv, qv) by J_v
-                    const double r00 = cv * m00 - sv * m01, r01 = sv * m00 + cv * m01;
-                    const double r10 = cv * m10 - sv * m11, r11 = sv * m10 + cv * m11;
+                    const double r00 = cv * m00[i] - sv * m01[i], r01 = sv * m00[i] + cv * m01[i];
+                    const double r10 = cv * m10[i] - sv * m11[i], r11 = sv * m10[i] + cv * m11[i];
                     // rows (pu, qu) by J_u^T
                     n00 = cu * r00 - su * r10;
                     n10 = su * r00 + cu * r10;
                     n01 = cu * r01 - su * r11;
                     n11 = su * r01 + cu * r11;
-                    S[pu * LDT + pv] = n00;
-                    S[pu * LDT + qv] = n01;
-                    S[qu * LDT + pv] = n10;
-                    S[qu * LDT + qv] = n11;
-                    S[pv * LDT + pu] = n00;
-                    S[qv * LDT + pu] = n01;
-                    S[pv * LDT + qu] = n10;
-                    S[qv * LDT + qu] = n11;
+                    S[pu[i] * LDT + pv] = n00;
+                    S[pu[i] * LDT + qv] = n01;
+                    S[qu[i] * LDT + pv] = n10;
+                    S[qu[i] * LDT + qv] = n11;
+                    S[pv * LDT + pu[i]] = n00;
+                    S[qv * LDT + pu[i]] = n01;
+                    S[pv * LDT + qu[i]] = n10;
+                    S[qv * LDT + qu[i]] = n11;
                 }
                 // Q <- Q J (columns p, q of every row)
-                for (int e = t; e < ET * EB; e += NT) {
-                    const int i = e / EB, u = e % EB;
-                    const int p = pp[u], q = qq[u];
-                    const double c = cc[u], s = ss[u];
-                    const double x = Q[i * LDT + p], y = Q[i * LDT + q];
-                    Q[i * LDT + p] = c * x - s * y;
-                    Q[i * LDT + q] = s * x + c * y;
+                if (qrot) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int i = t / EB + 8 * k;
+                        Q[i * LDT + pv] = cv * qx[k] - sv * qy[k];
+                        Q[i * LDT + qv] = sv * qx[k] + cv * qy[k];
+                    }
                 }
             }
             __syncthreads();
