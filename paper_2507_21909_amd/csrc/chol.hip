@@ -7,7 +7,10 @@
 // Right-looking, blocks of 64: the diagonal block is factorised in LDS by one
 // workgroup per matrix (which also inverts it), the panel below is multiplied
 // by that inverse (GEMM), and the trailing matrix takes the rank-64 update
-// (GEMM, alpha = -1, beta = 1).  A pivot that is not positive and finite marks
+// (GEMM, alpha = -1, beta = 1).  The pivoted variant (diagonal pivoting, as
+// LAPACK's dpstrf) factors each 64-column panel in one workgroup per matrix
+// and gives K = X X^T with X = P L, whose columns are graded like the
+// eigen-decomposition's W Lambda^{1/2}.  A pivot that is not positive and finite marks
 // the matrix in status[] (the caller then takes the eigen-decomposition route).
 #include <algorithm>
 #include <cmath>
@@ -71,6 +74,106 @@ __global__ __launch_bounds__(CT) void chol_diag_kernel(double *K, int n, int j0,
     }
 }
 
+// Pivoted panel: columns j0 .. j0 + nb - 1 of matrix blockIdx.x with diagonal
+// (symmetric) pivoting.  Before step j the trailing matrix A[j:, j:] holds K
+// minus the updates of all earlier panels (not yet those of this panel's
+// columns, which are applied to column j and to the diagonal as they are
+// needed).  Step j picks the largest remaining diagonal, swaps rows and
+// columns j and p of the whole matrix (and perm), and forms column j of L.
+__global__ __launch_bounds__(CT) void pchol_panel_kernel(double *K, int n, int j0, int nb, int *perm,
+                                                        int *status) {
+    __shared__ double dd[1024];
+    __shared__ double rowj[CB];
+    __shared__ double rv[CT / 64];
+    __shared__ int ri[CT / 64];
+    __shared__ int piv;
+    __shared__ double dpiv;
+    const int mat = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+    double *A = K + (size_t)mat * n * n;
+    int *pm = perm + (size_t)mat * n;
+    // diagonal of the trailing matrix, corrected for nothing yet in this panel
+    for (int i = j0 + t; i < n; i += CT) dd[i] = A[(size_t)i * n + i];
+    __syncthreads();
+    for (int j = j0; j < j0 + nb; ++j) {
+        // argmax of dd[j:] (ties: lowest index)
+        double bv = -1.0;
+        int bi = j;
+        for (int i = j + t; i < n; i += CT)
+            if (dd[i] > bv) { bv = dd[i]; bi = i; }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if (lane == 0) { rv[w] = bv; ri[w] = bi; }
+        __syncthreads();
+        if (t == 0) {
+            double v = rv[0];
+            int id = ri[0];
+            for (int x = 1; x < CT / 64; ++x)
+                if (rv[x] > v || (rv[x] == v && ri[x] < id)) { v = rv[x]; id = ri[x]; }
+            piv = id;
+            dpiv = v;
+            if (!(v > 0.0) || !isfinite(v)) status[mat] = 1;
+        }
+        __syncthreads();
+        if (!(dpiv > 0.0) || !isfinite(dpiv)) return;   // uniform: the caller falls back
+        const int p = piv;
+        if (p != j) {
+            for (int c = t; c < n; c += CT) {
+                const double x = A[(size_t)j * n + c];
+                A[(size_t)j * n + c] = A[(size_t)p * n + c];
+                A[(size_t)p * n + c] = x;
+            }
+            __syncthreads();
+            for (int r = t; r < n; r += CT) {
+                const double x = A[(size_t)r * n + j];
+                A[(size_t)r * n + j] = A[(size_t)r * n + p];
+                A[(size_t)r * n + p] = x;
+            }
+            if (t == 0) {
+                const double x = dd[j];
+                dd[j] = dd[p];
+                dd[p] = x;
+                const int y = pm[j];
+                pm[j] = pm[p];
+                pm[p] = y;
+            }
+            __syncthreads();
+        }
+        // row j of this panel's earlier columns
+        if (t < j - j0) rowj[t] = A[(size_t)j * n + j0 + t];
+        __syncthreads();
+        const double ljj = sqrt(dd[j]);
+        if (t == 0) A[(size_t)j * n + j] = ljj;
+        for (int i = j + 1 + t; i < n; i += CT) {
+            double a = A[(size_t)i * n + j];
+            const double *li = A + (size_t)i * n + j0;
+            for (int k = 0; k < j - j0; ++k) a -= li[k] * rowj[k];
+            a /= ljj;
+            A[(size_t)i * n + j] = a;
+            dd[i] -= a * a;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void perm_init_kernel(int *perm, int n, int count) {
+    const long tot = (long)count * n;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x)
+        perm[e] = (int)(e % n);
+}
+
+// X[perm[i], :] = L[i, :] (K = X X^T with X = P L)
+__global__ void unpermute_rows_kernel(const double *L, const int *perm, int n, int count, double *X) {
+    const long tot = (long)count * n * n;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const long mat = e / ((long)n * n), rem = e % ((long)n * n);
+        const int i = (int)(rem / n), c = (int)(rem % n);
+        X[mat * n * n + (long)perm[mat * n + i] * n + c] = L[e];
+    }
+}
+
 __global__ void zero_upper_kernel(double *K, int n, int count) {
     const long tot = (long)count * n * n;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
@@ -82,6 +185,39 @@ __global__ void zero_upper_kernel(double *K, int n, int count) {
 }  // namespace
 
 size_t chol_ws_doubles(int count, int n) { return (size_t)count * (CB * CB + (size_t)n * CB) + 64; }
+
+size_t pchol_iws_ints(int count, int n) { return (size_t)count * (n + 1) + 16; }
+
+bool pivoted_cholesky_batched(double *K, int count, int n, double *X, int *iws, hipStream_t st) {
+    if (count == 0 || n == 0) return true;
+    TRG_REQUIRE(n <= 1024, -6, "pivoted Cholesky: n > 1024");
+    int *status = iws, *perm = iws + count;
+    TRG_HIP_CHECK(hipMemsetAsync(status, 0, sizeof(int) * count, st));
+    const unsigned gb = (unsigned)std::min<size_t>(((size_t)count * n * n + 255) / 256, 65536);
+    hipLaunchKernelGGL(perm_init_kernel, dim3(gb), dim3(256), 0, st, perm, n, count);
+    for (int j0 = 0; j0 < n; j0 += CB) {
+        const int nb = std::min(CB, n - j0), rows = n - j0 - nb;
+        hipLaunchKernelGGL(pchol_panel_kernel, dim3(count), dim3(CT), 0, st, K, n, j0, nb, perm, status);
+        TRG_HIP_CHECK(hipGetLastError());
+        if (rows == 0) break;
+        GemmArgs h{};
+        h.M = rows; h.N = rows; h.K = nb; h.batch = count;
+        h.A = K + (size_t)(j0 + nb) * n + j0; h.sAr = n; h.sAk = 1; h.sAb = (long)n * n;
+        h.B = K + (size_t)(j0 + nb) * n + j0; h.sBk = 1; h.sBn = n; h.sBb = (long)n * n;
+        h.C = K + (size_t)(j0 + nb) * n + j0 + nb; h.sCr = n; h.sCn = 1; h.sCb = (long)n * n;
+        h.alpha = -1.0; h.beta = 1.0;
+        gemm(h, P_FP64, st);
+    }
+    hipLaunchKernelGGL(zero_upper_kernel, dim3(gb), dim3(256), 0, st, K, n, count);
+    hipLaunchKernelGGL(unpermute_rows_kernel, dim3(gb), dim3(256), 0, st, K, perm, n, count, X);
+    TRG_HIP_CHECK(hipGetLastError());
+    std::vector<int> fl(count);
+    TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), status, sizeof(int) * count, hipMemcpyDeviceToHost, st));
+    TRG_HIP_CHECK(hipStreamSynchronize(st));
+    for (int f : fl)
+        if (f) return false;
+    return true;
+}
 
 bool cholesky_batched(double *K, int count, int n, double *ws, int *status_dev, hipStream_t st) {
     if (count == 0 || n == 0) return true;

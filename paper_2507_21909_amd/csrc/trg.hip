@@ -458,11 +458,22 @@ void squeezers(Step &T, const double *kf, const double *kb, int cnt, int dt, int
         copy(kk + (2 * i) * nn, kf + i * nn, nn, c.st);
         copy(kk + (2 * i + 1) * nn, kb + i * nn, nn, c.st);
     }
+    // pivoted Cholesky (X = P L, columns graded like W Lambda^{1/2}) keeps the
+    // one-sided Jacobi of X_f^T X_b at about half the sweeps of plain Cholesky
     double *xs = c.ar->dalloc(2 * cnt * nn);
-    copy(xs, kk, 2 * cnt * nn, c.st);
-    int *cst = reinterpret_cast<int *>(c.ar->dalloc(cnt + 1));
-    double *cws = c.ar->dalloc(chol_ws_doubles(2 * cnt, n));
-    if (!cholesky_batched(xs, 2 * cnt, n, cws, cst, c.st)) {
+    bool chol_ok;
+    if (n <= 1024) {
+        double *kw = c.ar->dalloc(2 * cnt * nn);
+        copy(kw, kk, 2 * cnt * nn, c.st);
+        int *piws = reinterpret_cast<int *>(c.ar->dalloc((pchol_iws_ints(2 * cnt, n) + 1) / 2));
+        chol_ok = pivoted_cholesky_batched(kw, 2 * cnt, n, xs, piws, c.st);
+    } else {
+        copy(xs, kk, 2 * cnt * nn, c.st);
+        int *cst = reinterpret_cast<int *>(c.ar->dalloc(cnt + 1));
+        double *cws = c.ar->dalloc(chol_ws_doubles(2 * cnt, n));
+        chol_ok = cholesky_batched(xs, 2 * cnt, n, cws, cst, c.st);
+    }
+    if (!chol_ok) {
         DT lam = talloc(c, {2 * cnt, n}), sq = talloc(c, {2 * cnt, n});
         eig_psd(T, kk, 2 * cnt, n, lam.p, xs);
         for (int i = 0; i < 2 * cnt; ++i) {
