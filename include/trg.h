@@ -188,7 +188,7 @@ const char *trg_last_error(trg_state *s);
 int trg_selftest_gemm(int precision, int ta, int tb, int M, int N, int K, int batch,
                       const double *A, const double *B, double *C);
 
-/* Thin QR of A (m x n, m >= n, n <= 64) by the LDS Householder TSQR:
+/* Thin QR of A (m x n, m >= n, n <= 64) by the register-resident Householder TSQR:
  * Q (m x n), R (n x n) with diag(R) >= 0. */
 int trg_selftest_tsqr(int m, int n, const double *A, double *Q, double *R);
 
@@ -201,6 +201,22 @@ int trg_selftest_svd(int m, int n, const double *A, double *U, double *s, double
  * descending, V (count x n x n) with eigenvector j in column j.  Returns the
  * number of sweeps in *sweeps. */
 int trg_selftest_eigh(int count, int n, const double *K, double *lam, double *V, int *sweeps);
+
+/* Diagonally pivoted Cholesky factor of `count` symmetric positive
+ * semi-definite n x n matrices K (n <= 1024, batch stride n*n): X (count x n
+ * x n) with K = X X^T, X = P L (P a row permutation, L lower triangular).  A
+ * matrix's factorisation stops at its first pivot at or below tol times its
+ * first (largest) pivot, 0 <= tol < 1, and the columns of X from there on are
+ * zero; rank (count ints) receives the columns formed.  TRG_E_NUMERICAL for a
+ * pivot that is not finite, or, with tol = 0, not positive. */
+int trg_selftest_pchol(int count, int n, const double *K, double tol, double *X, int *rank);
+
+/* Eigen-decomposition of `count` symmetric positive semi-definite n x n Grams
+ * K (n <= 1024) as the triad isometries take it: one-sided Jacobi SVD of the
+ * pivoted Cholesky factor X (K = X X^T), eigenvectors the left singular
+ * vectors, eigenvalues the squared singular values.  lam, V and *sweeps as
+ * for trg_selftest_eigh. */
+int trg_selftest_gram_eig(int count, int n, const double *K, double *lam, double *V, int *sweeps);
 
 /* Gaussian sketch entries Omega[beta, j1, j2, j3, m] (layout as named) drawn
  * exactly as the bond swap of step `step` draws them. */

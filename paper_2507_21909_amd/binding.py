@@ -78,6 +78,9 @@ def load_library(path=None):
     lib.trg_selftest_tsqr.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP]
     lib.trg_selftest_svd.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP, _DP, ctypes.POINTER(ctypes.c_int)]
     lib.trg_selftest_eigh.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP, ctypes.POINTER(ctypes.c_int)]
+    lib.trg_selftest_pchol.argtypes = [ctypes.c_int, ctypes.c_int, _DP, ctypes.c_double, _DP,
+                                       ctypes.POINTER(ctypes.c_int)]
+    lib.trg_selftest_gram_eig.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP, ctypes.POINTER(ctypes.c_int)]
     lib.trg_selftest_sketch.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32] + [ctypes.c_int] * 5 + [_DP]
     lib.trg_batch_create.argtypes = [ctypes.c_int, _DP, _DP, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
                                      ctypes.POINTER(ctypes.c_void_p)]
@@ -91,7 +94,8 @@ def load_library(path=None):
         getattr(lib, f).restype = ctypes.c_int
     for f in ("trg_create", "trg_destroy", "tensor_init", "atrg_step", "triad_atrg_step", "log_z_per_site",
               "trg_shape", "trg_export", "trg_set_timing", "trg_kernel_time", "trg_selftest_gemm",
-              "trg_selftest_tsqr", "trg_selftest_svd", "trg_selftest_eigh", "trg_selftest_sketch"):
+              "trg_selftest_tsqr", "trg_selftest_svd", "trg_selftest_eigh", "trg_selftest_pchol",
+              "trg_selftest_gram_eig", "trg_selftest_sketch"):
         getattr(lib, f).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -273,6 +277,39 @@ def selftest_eigh(k):
     v = np.empty((count, n, n))
     sw = ctypes.c_int(0)
     _check(lib.trg_selftest_eigh(count, n, _p(kb), _p(lam), _p(v), ctypes.byref(sw)))
+    return (lam[0], v[0], sw.value) if single else (lam, v, sw.value)
+
+
+def _square_batch(k):
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    single = k.ndim == 2
+    kb = k[None] if single else k
+    if kb.ndim != 3 or kb.shape[2] != kb.shape[1]:
+        raise ValueError("square matrices required")
+    return kb, single
+
+
+def selftest_pchol(k, tol=0.0):
+    """Pivoted Cholesky factors X (K = X X^T, X = P L) and ranks of PSD matrices k."""
+    lib = load_library()
+    kb, single = _square_batch(k)
+    count, n = kb.shape[0], kb.shape[1]
+    x = np.empty((count, n, n))
+    rank = (ctypes.c_int * count)()
+    _check(lib.trg_selftest_pchol(count, n, _p(kb), float(tol), _p(x), rank))
+    rk = list(rank)
+    return (x[0], rk[0]) if single else (x, rk)
+
+
+def selftest_gram_eig(k):
+    """Eigen-decomposition of PSD Grams k through their pivoted Cholesky factors."""
+    lib = load_library()
+    kb, single = _square_batch(k)
+    count, n = kb.shape[0], kb.shape[1]
+    lam = np.empty((count, n))
+    v = np.empty((count, n, n))
+    sw = ctypes.c_int(0)
+    _check(lib.trg_selftest_gram_eig(count, n, _p(kb), _p(lam), _p(v), ctypes.byref(sw)))
     return (lam[0], v[0], sw.value) if single else (lam, v, sw.value)
 
 

@@ -11,9 +11,15 @@
 // LAPACK's dpstrf) factors each 64-column panel in one workgroup per matrix
 // and gives K = X X^T with X = P L, whose columns are graded like the
 // eigen-decomposition's W Lambda^{1/2}.  A pivot that is not positive and finite marks
-// the matrix in status[] (the caller then takes the eigen-decomposition route).
+// the matrix in status[] (the caller then takes the eigen-decomposition route),
+// unless a relative tolerance is given: then the factorisation of a matrix stops
+// at the first pivot at or below tol times its first (largest) one, and the
+// columns from there on are zero.  The Schur complement left out is positive
+// semi-definite with every diagonal entry at or below that pivot, so for a
+// tolerance at the rounding level of K the truncated X X^T is K to that level.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 
 #include "common.h"
 
@@ -80,17 +86,22 @@ __global__ __launch_bounds__(CT) void chol_diag_kernel(double *K, int n, int j0,
 // columns, which are applied to column j and to the diagonal as they are
 // needed).  Step j picks the largest remaining diagonal, swaps rows and
 // columns j and p of the whole matrix (and perm), and forms column j of L.
+// rk[mat]: columns formed (n unless the factorisation stopped); dtop[mat]: the first pivot.
 __global__ __launch_bounds__(CT) void pchol_panel_kernel(double *K, int n, int j0, int nb, int *perm,
-                                                        int *status) {
+                                                        int *status, int *rk, double *dtop, double tol) {
     __shared__ double dd[1024];
     __shared__ double rowj[CB];
     __shared__ double rv[CT / 64];
     __shared__ int ri[CT / 64];
     __shared__ int piv;
     __shared__ double dpiv;
+    __shared__ double d0;
+    __shared__ int stop;
     const int mat = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (rk[mat] < n || status[mat]) return;   // stopped in an earlier panel
     double *A = K + (size_t)mat * n * n;
     int *pm = perm + (size_t)mat * n;
+    if (t == 0) d0 = j0 > 0 ? dtop[mat] : 0.0;
     // diagonal of the trailing matrix, corrected for nothing yet in this panel
     for (int i = j0 + t; i < n; i += CT) dd[i] = A[(size_t)i * n + i];
     __syncthreads();
@@ -114,10 +125,21 @@ __global__ __launch_bounds__(CT) void pchol_panel_kernel(double *K, int n, int j
                 if (rv[x] > v || (rv[x] == v && ri[x] < id)) { v = rv[x]; id = ri[x]; }
             piv = id;
             dpiv = v;
-            if (!(v > 0.0) || !isfinite(v)) status[mat] = 1;
+            if (j == 0) {
+                d0 = v;
+                dtop[mat] = v;
+            }
+            int st = 0;
+            if (!isfinite(v))
+                st = 1;
+            else if (tol > 0.0 ? v <= tol * d0 : !(v > 0.0))
+                st = tol > 0.0 ? 2 : 1;
+            if (st == 1) status[mat] = 1;   // the caller falls back
+            if (st == 2) rk[mat] = j;       // rank j: columns j.. stay zero
+            stop = st;
         }
         __syncthreads();
-        if (!(dpiv > 0.0) || !isfinite(dpiv)) return;   // uniform: the caller falls back
+        if (stop) return;   // uniform
         const int p = piv;
         if (p != j) {
             for (int c = t; c < n; c += CT) {
@@ -158,10 +180,15 @@ __global__ __launch_bounds__(CT) void pchol_panel_kernel(double *K, int n, int j
     }
 }
 
-__global__ void perm_init_kernel(int *perm, int n, int count) {
+__global__ void perm_init_kernel(int *perm, int *rk, int *status, int n, int count) {
     const long tot = (long)count * n;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x)
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
         perm[e] = (int)(e % n);
+        if (e < count) {
+            rk[e] = n;
+            status[e] = 0;
+        }
+    }
 }
 
 // X[perm[i], :] = L[i, :] (K = X X^T with X = P L)
@@ -174,30 +201,36 @@ __global__ void unpermute_rows_kernel(const double *L, const int *perm, int n, i
     }
 }
 
-__global__ void zero_upper_kernel(double *K, int n, int count) {
+// zero above the diagonal and, with rk, the columns past each matrix's rank
+__global__ void zero_upper_kernel(double *K, int n, int count, const int *rk) {
     const long tot = (long)count * n * n;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
-        const long rem = e % ((long)n * n);
+        const long mat = e / ((long)n * n), rem = e % ((long)n * n);
         const int i = (int)(rem / n), j = (int)(rem % n);
-        if (j > i) K[e] = 0.0;
+        if (j > i || (rk && j >= rk[mat])) K[e] = 0.0;
     }
 }
 }  // namespace
 
 size_t chol_ws_doubles(int count, int n) { return (size_t)count * (CB * CB + (size_t)n * CB) + 64; }
 
-size_t pchol_iws_ints(int count, int n) { return (size_t)count * (n + 1) + 16; }
+// ints: dtop (count doubles), status (count), rk (count), perm (count * n)
+size_t pchol_iws_ints(int count, int n) { return (size_t)count * (n + 4) + 16; }
 
-bool pivoted_cholesky_batched(double *K, int count, int n, double *X, int *iws, hipStream_t st) {
+bool pivoted_cholesky_batched(double *K, int count, int n, double *X, int *iws, hipStream_t st, double tol,
+                              int *rank) {
     if (count == 0 || n == 0) return true;
     TRG_REQUIRE(n <= 1024, -6, "pivoted Cholesky: n > 1024");
-    int *status = iws, *perm = iws + count;
-    TRG_HIP_CHECK(hipMemsetAsync(status, 0, sizeof(int) * count, st));
+    TRG_REQUIRE(tol >= 0.0 && tol < 1.0, -1, "pivoted Cholesky: tolerance outside [0, 1)");
+    TRG_REQUIRE(reinterpret_cast<uintptr_t>(iws) % alignof(double) == 0, -1, "pivoted Cholesky: iws not 8-aligned");
+    double *dtop = reinterpret_cast<double *>(iws);
+    int *status = iws + 2 * count, *rk = status + count, *perm = rk + count;
     const unsigned gb = (unsigned)std::min<size_t>(((size_t)count * n * n + 255) / 256, 65536);
-    hipLaunchKernelGGL(perm_init_kernel, dim3(gb), dim3(256), 0, st, perm, n, count);
+    hipLaunchKernelGGL(perm_init_kernel, dim3(gb), dim3(256), 0, st, perm, rk, status, n, count);
     for (int j0 = 0; j0 < n; j0 += CB) {
         const int nb = std::min(CB, n - j0), rows = n - j0 - nb;
-        hipLaunchKernelGGL(pchol_panel_kernel, dim3(count), dim3(CT), 0, st, K, n, j0, nb, perm, status);
+        hipLaunchKernelGGL(pchol_panel_kernel, dim3(count), dim3(CT), 0, st, K, n, j0, nb, perm, status, rk, dtop,
+                           tol);
         TRG_HIP_CHECK(hipGetLastError());
         if (rows == 0) break;
         GemmArgs h{};
@@ -208,14 +241,15 @@ bool pivoted_cholesky_batched(double *K, int count, int n, double *X, int *iws, 
         h.alpha = -1.0; h.beta = 1.0;
         gemm(h, P_FP64, st);
     }
-    hipLaunchKernelGGL(zero_upper_kernel, dim3(gb), dim3(256), 0, st, K, n, count);
+    hipLaunchKernelGGL(zero_upper_kernel, dim3(gb), dim3(256), 0, st, K, n, count, rk);
     hipLaunchKernelGGL(unpermute_rows_kernel, dim3(gb), dim3(256), 0, st, K, perm, n, count, X);
     TRG_HIP_CHECK(hipGetLastError());
-    std::vector<int> fl(count);
-    TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), status, sizeof(int) * count, hipMemcpyDeviceToHost, st));
+    std::vector<int> fl(2 * count);   // status, then rk
+    TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), status, sizeof(int) * 2 * count, hipMemcpyDeviceToHost, st));
     TRG_HIP_CHECK(hipStreamSynchronize(st));
-    for (int f : fl)
-        if (f) return false;
+    if (rank) std::copy(fl.begin() + count, fl.end(), rank);
+    for (int i = 0; i < count; ++i)
+        if (fl[i]) return false;
     return true;
 }
 
@@ -250,7 +284,7 @@ bool cholesky_batched(double *K, int count, int n, double *ws, int *status_dev, 
         gemm(h, P_FP64, st);
     }
     hipLaunchKernelGGL(zero_upper_kernel, dim3(std::min<size_t>(((size_t)count * n * n + 255) / 256, 65536)),
-                       dim3(256), 0, st, K, n, count);
+                       dim3(256), 0, st, K, n, count, nullptr);
     TRG_HIP_CHECK(hipGetLastError());
     std::vector<int> fl(count);
     TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), status_dev, sizeof(int) * count, hipMemcpyDeviceToHost, st));

@@ -122,10 +122,14 @@ int eigh_sym(const double *K, int count, int n, double *lam, double *vec, double
 size_t chol_ws_doubles(int count, int n);
 bool cholesky_batched(double *K, int count, int n, double *ws, int *status_dev, hipStream_t st);
 // Pivoted variant: K (count x n x n, n <= 1024) is overwritten; X (count x n x n)
-// receives X = P L with K = X X^T.  iws: pchol_iws_ints ints.  false if a pivot
-// was not positive and finite (X then undefined).
+// receives X = P L with K = X X^T.  iws: pchol_iws_ints ints, 8-byte aligned.
+// tol = 0: false if a pivot was not positive and finite (X then undefined).
+// tol > 0: a matrix's factorisation stops at the first pivot at or below tol
+// times its first pivot and the remaining columns of X are zero; false only for
+// a non-finite pivot.  rank (host, count ints, optional): columns formed.
 size_t pchol_iws_ints(int count, int n);
-bool pivoted_cholesky_batched(double *K, int count, int n, double *X, int *iws, hipStream_t st);
+bool pivoted_cholesky_batched(double *K, int count, int n, double *X, int *iws, hipStream_t st, double tol = 0.0,
+                              int *rank = nullptr);
 void jacobi_finish(const JacobiBatch &jb, double *s, double *u_sorted, double *v_sorted,
                    double *work, hipStream_t st);
 

@@ -39,6 +39,9 @@ namespace trg {
 namespace {
 
 constexpr double EPS_S = 1e-14, EPS_LAM = 1e-14, EPS_SQ = 1e-14, TAU_DEG_DEFAULT = 1e-9;
+// pivoted Cholesky of a Gram stops at pivots at the rounding level of its largest
+// entry (the Gram itself is only known to about that)
+constexpr double PCHOL_TOL = 2.220446049250313e-16;
 
 // ---------------------------------------------------------------- small kernels
 __global__ void resplit_norm_kernel(double *s, int n, int k, double *logacc, double eps, int *status) {
@@ -190,6 +193,40 @@ void eig_psd(Step &T, const double *k, int count, int n, double *lam, double *ve
     int *iws = reinterpret_cast<int *>(c.ar->dalloc((eigh_iws_ints(count, n) + 1) / 2));
     int ms = T.S->opt.max_sweeps > 0 ? T.S->opt.max_sweeps : 300;
     eigh_sym(k, count, n, lam, vec, ws, iws, ms, c.st);
+}
+
+// Eigen-decomposition of symmetric PSD Grams K = X X^T (count x n x n, n <= 1024)
+// through the pivoted Cholesky factor X = P L: K's eigenvectors are X's left
+// singular vectors and its eigenvalues X's squared singular values.  X's
+// columns come graded (pivot order), and the one-sided solver on them needs
+// about half the sweeps of the two-sided solver on K.  Pivots at or below
+// PCHOL_TOL of the first end the factor (the rest of the spectrum is then
+// zero).  lam desc, vec row-major (columns), as eig_psd.  false (lam, vec
+// untouched) if n > 1024 or a pivot is not finite.
+bool gram_eig_pchol(Ctx &c, const double *k, int count, int n, int max_sweeps, double *lam, double *vec,
+                    int *sweeps) {
+    if (n > 1024) return false;
+    const size_t nn = (size_t)n * n;
+    Arena::Mark mk = c.ar->mark();
+    double *kw = c.ar->dalloc(count * nn), *xs = c.ar->dalloc(count * nn);
+    copy(kw, k, count * nn, c.st);
+    int *piws = reinterpret_cast<int *>(c.ar->dalloc((pchol_iws_ints(count, n) + 1) / 2));
+    if (!pivoted_cholesky_batched(kw, count, n, xs, piws, c.st, PCHOL_TOL)) {
+        c.ar->release(mk);
+        return false;
+    }
+    // the one-sided solver takes column-major matrices: X^T row-major
+    permute(xs, kw, {count, n, n}, {0, 2, 1}, c.st);
+    double *work = c.ar->dalloc((size_t)count * (n + 1)), *s = c.ar->dalloc((size_t)count * n);
+    int *flags = reinterpret_cast<int *>(c.ar->dalloc((size_t)count));   // 2 * count ints
+    JacobiBatch jb{count, n, n, kw, nullptr, (long)nn, (long)nn};
+    const int sw = jacobi_svd(jb, max_sweeps, flags, work, c.st);
+    jacobi_finish(jb, s, vec, nullptr, work, c.st);
+    hipLaunchKernelGGL(square_kernel, dim3(g1(count * n)), dim3(256), 0, c.st, s, lam, count * n);
+    TRG_HIP_CHECK(hipGetLastError());
+    if (sweeps) *sweeps = sw;
+    c.ar->release(mk);
+    return true;
 }
 
 // ---------------------------------------------------------------- re-split
@@ -449,7 +486,8 @@ void squeezers(Step &T, const double *kf, const double *kb, int cnt, int dt, int
     const int n = dt * db, D = S->D;
     const size_t nn = (size_t)n * n;
     // square-root factors X (K = X X^T) of all K_f, K_b in one batch, [f0, b0, f1, b1, ...]:
-    // R = X^T.  Cholesky when every Gram is positive definite; otherwise
+    // R = X^T.  Pivoted Cholesky (stopped at rounding-level pivots) for n <= 1024,
+    // plain Cholesky above when every Gram is positive definite; otherwise
     // X = W Lambda^{1/2} from the eigen-decomposition with eigenvalues at or
     // below EPS_LAM of the largest set to zero.  Any two square roots of K
     // differ by an orthogonal factor, which cancels in E and F below.
@@ -466,7 +504,7 @@ void squeezers(Step &T, const double *kf, const double *kb, int cnt, int dt, int
         double *kw = c.ar->dalloc(2 * cnt * nn);
         copy(kw, kk, 2 * cnt * nn, c.st);
         int *piws = reinterpret_cast<int *>(c.ar->dalloc((pchol_iws_ints(2 * cnt, n) + 1) / 2));
-        chol_ok = pivoted_cholesky_batched(kw, 2 * cnt, n, xs, piws, c.st);
+        chol_ok = pivoted_cholesky_batched(kw, 2 * cnt, n, xs, piws, c.st, PCHOL_TOL);
     } else {
         copy(xs, kk, 2 * cnt * nn, c.st);
         int *cst = reinterpret_cast<int *>(c.ar->dalloc(cnt + 1));
@@ -630,7 +668,8 @@ void triad_isos(Step &T, const DT *grams, int d1, int d2, int rcap, DT *U) {
     double *kk = c.ar->dalloc(4 * nn);
     for (int i = 0; i < 4; ++i) copy(kk + i * nn, grams[i].p, nn, c.st);
     DT lam = talloc(c, {4, n}), vec = talloc(c, {4, n, n});
-    eig_psd(T, kk, 4, n, lam.p, vec.p);
+    const int ms = T.S->opt.max_sweeps > 0 ? T.S->opt.max_sweeps : 300;
+    if (!gram_eig_pchol(c, kk, 4, n, ms, lam.p, vec.p, nullptr)) eig_psd(T, kk, 4, n, lam.p, vec.p);
     for (int i = 0; i < 4; ++i) {
         int *kept = T.new_kept();
         kept_count(lam.p + (size_t)i * n, n, rcap, EPS_LAM, T.S->opt.tau_deg, kept, c.st);
@@ -1189,6 +1228,49 @@ int trg_selftest_eigh(int count, int n, const double *K, double *lam, double *V,
         double *ws = s.ar.dalloc(trg::eigh_ws_doubles(count, n));
         int *iws = static_cast<int *>(s.ar.alloc(trg::eigh_iws_ints(count, n) * sizeof(int)));
         int sw = trg::eigh_sym(k, count, n, l, v, ws, iws, 100, nullptr);
+        s.down(lam, l, (size_t)count * n);
+        s.down(V, v, nn);
+        if (sweeps) *sweeps = sw;
+    } catch (const Error &e) {
+        g_err = e.what();
+        return e.code;
+    }
+    return TRG_OK;
+}
+
+int trg_selftest_pchol(int count, int n, const double *K, double tol, double *X, int *rank) {
+    if (!K || !X || !rank || n < 1 || count < 1 || !(tol >= 0.0 && tol < 1.0)) return TRG_E_INVALID;
+    if (n > 1024) return TRG_E_UNSUPPORTED;
+    try {
+        Scratch s;
+        const size_t nn = (size_t)count * n * n;
+        double *k = s.up(K, nn), *x = s.ar.dalloc(nn);
+        int *iws = reinterpret_cast<int *>(s.ar.dalloc((trg::pchol_iws_ints(count, n) + 1) / 2));
+        if (!trg::pivoted_cholesky_batched(k, count, n, x, iws, nullptr, tol, rank)) {
+            g_err = "pivoted Cholesky: pivot not finite (or not positive with tol = 0)";
+            return TRG_E_NUMERICAL;
+        }
+        s.down(X, x, nn);
+    } catch (const Error &e) {
+        g_err = e.what();
+        return e.code;
+    }
+    return TRG_OK;
+}
+
+int trg_selftest_gram_eig(int count, int n, const double *K, double *lam, double *V, int *sweeps) {
+    if (!K || !lam || !V || n < 1 || count < 1) return TRG_E_INVALID;
+    if (n > 1024) return TRG_E_UNSUPPORTED;
+    try {
+        Scratch s;
+        const size_t nn = (size_t)count * n * n;
+        double *k = s.up(K, nn);
+        double *l = s.ar.dalloc((size_t)count * n), *v = s.ar.dalloc(nn);
+        int sw = 0;
+        if (!trg::gram_eig_pchol(s.c, k, count, n, 100, l, v, &sw)) {
+            g_err = "gram eigen-decomposition: pivot not finite";
+            return TRG_E_NUMERICAL;
+        }
         s.down(lam, l, (size_t)count * n);
         s.down(V, v, nn);
         if (sweeps) *sweeps = sw;

@@ -169,6 +169,101 @@ def test_block_jacobi_eigh_degenerate():
     assert np.max(np.abs(p - p0)) < 1e-12
 
 
+def _lower_up_to_rows(x):
+    """Rows of X = P L reordered into L: row r of L ends at column r, so each
+    row's last nonzero column names its place (-1 for a zero row)."""
+    n = x.shape[0]
+    last = np.array([np.flatnonzero(x[i])[-1] if np.any(x[i]) else -1 for i in range(n)])
+    return last
+
+
+@pytest.mark.parametrize("n,count", [(1, 1), (63, 2), (200, 3), (1024, 2)])
+def test_pivoted_cholesky_full_rank(n, count):
+    _say("pchol", n, count)
+    rng = np.random.default_rng(100 + n)
+    a = rng.standard_normal((count, n, n + 8))
+    k = a @ a.transpose(0, 2, 1)
+    x, rank = trg.selftest_pchol(k, tol=0.0)
+    for b in range(count):
+        scale = np.max(np.abs(k[b]))
+        assert rank[b] == n
+        assert np.max(np.abs(x[b] @ x[b].T - k[b])) < 20 * n * 2.2e-16 * scale
+        # X = P L with L lower triangular: the rows' last nonzero columns are a permutation
+        last = _lower_up_to_rows(x[b])
+        assert sorted(last) == list(range(n))
+        # diagonal pivoting: L's diagonal is positive and non-increasing
+        diag = np.array([x[b][np.flatnonzero(last == j)[0], j] for j in range(n)])
+        assert np.all(diag > 0) and np.all(np.diff(diag) <= 1e-12 * diag[0])
+
+
+def test_pivoted_cholesky_truncates_at_tolerance():
+    """Rank 120 in 300 dims, spectrum graded over 10 decades: the factor stops at
+    a rounding-level pivot and its columns from there on are exactly zero."""
+    rng = np.random.default_rng(41)
+    n, r = 300, 120
+    q, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    g = (q * (10.0 ** -np.linspace(0, 10, r))) @ q.T
+    z = np.zeros((n, n))
+    x, rank = trg.selftest_pchol(np.stack([g, z]), tol=2.220446049250313e-16)
+    assert r <= rank[0] < n
+    assert np.all(x[0][:, rank[0]:] == 0.0)
+    assert np.max(np.abs(x[0] @ x[0].T - g)) < 20 * n * 2.2e-16
+    # the zero matrix has rank 0 and factor 0
+    assert rank[1] == 0 and np.all(x[1] == 0.0)
+    # without a tolerance a zero pivot is an error
+    with pytest.raises(trg.TrgError):
+        trg.selftest_pchol(z, tol=0.0)
+
+
+def test_gram_eig_graded_rank_deficient():
+    """The triad-isometry route (pivoted Cholesky, then one-sided Jacobi on the
+    factor) on a Gram of rank 120 in 520 dims graded over 12 decades."""
+    rng = np.random.default_rng(31)
+    n, k = 520, 120
+    qx, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    sv = 10.0 ** -np.linspace(0, 6, k)
+    g = (qx * sv ** 2) @ qx.T
+    lam, v, sweeps = trg.selftest_gram_eig(g)
+    assert sweeps < 30
+    ref = np.linalg.eigvalsh(g)[::-1]
+    floor = 20 * n * 2.2e-16
+    assert np.all(np.diff(lam) <= 0) and np.all(lam >= 0)
+    assert np.max(np.abs(lam - ref)) < floor
+    assert np.max(np.abs(lam[:k] - sv ** 2)) < floor
+    for j in range(0, k, 7):
+        if sv[j] ** 2 > 1e-4:
+            assert abs(abs(v[:, j] @ qx[:, j]) - 1.0) < 1e-8
+    # the kept part of the basis is orthonormal and satisfies g v = v lam
+    vk = v[:, :k]
+    assert np.max(np.abs(vk.T @ vk - np.eye(k))) < 1e-12
+    assert np.max(np.abs(g @ vk - vk * lam[:k])) < floor
+
+
+def test_gram_eig_triad_shape():
+    """Four 1024 x 1024 Grams of rank 1023 with a steep graded spectrum, the shape
+    of the D = 32 triad Grams: eigenvalues to the rounding floor, the leading 224
+    eigenvectors up to sign, in far fewer sweeps than the two-sided solver."""
+    rng = np.random.default_rng(77)
+    n, count = 1024, 4
+    sv = np.exp(-np.linspace(0, 18, n - 1))
+    gs, qs = [], []
+    for b in range(count):
+        q, _ = np.linalg.qr(rng.standard_normal((n, n - 1)))
+        qs.append(q)
+        gs.append((q * sv ** 2) @ q.T)
+    g = np.stack(gs)
+    lam, v, sweeps = trg.selftest_gram_eig(g)
+    _say("gram eig sweeps", sweeps)
+    assert sweeps <= 20
+    floor = 20 * n * 2.2e-16
+    for b in range(count):
+        assert np.max(np.abs(lam[b][:n - 1] - sv ** 2)) < floor
+        ov = np.abs(np.sum(v[b][:, :224] * qs[b][:, :224], axis=0))
+        assert np.max(np.abs(ov - 1.0)) < 1e-9
+        vk = v[b][:, :224]
+        assert np.max(np.abs(vk.T @ vk - np.eye(224))) < 1e-12
+
+
 def test_sketch_matches_oracle():
     _say("sketch")
     g = trg.selftest_sketch(0x2507219090000000, 5, 3, 7, (5, 4, 3), 9)
