@@ -8,9 +8,10 @@
 // workgroup per matrix (which also inverts it), the panel below is multiplied
 // by that inverse (GEMM), and the trailing matrix takes the rank-64 update
 // (GEMM, alpha = -1, beta = 1).  The pivoted variant (diagonal pivoting, as
-// LAPACK's dpstrf) factors each 64-column panel in one workgroup per matrix
-// and gives K = X X^T with X = P L, whose columns are graded like the
-// eigen-decomposition's W Lambda^{1/2}.  A pivot that is not positive and finite marks
+// LAPACK's dpstrf) factors 24-column panels in one 1024-thread workgroup per
+// matrix, each row in one thread's registers, and gives K = X X^T with
+// X = P L, whose columns are graded like the eigen-decomposition's
+// W Lambda^{1/2}.  A pivot that is not positive and finite marks
 // the matrix in status[] (the caller then takes the eigen-decomposition route),
 // unless a relative tolerance is given: then the factorisation of a matrix stops
 // at the first pivot at or below tol times its first (largest) one, and the
@@ -80,103 +81,108 @@ __global__ __launch_bounds__(CT) void chol_diag_kernel(double *K, int n, int j0,
     }
 }
 
-// Pivoted panel: columns j0 .. j0 + nb - 1 of matrix blockIdx.x with diagonal
-// (symmetric) pivoting.  Before step j the trailing matrix A[j:, j:] holds K
-// minus the updates of all earlier panels (not yet those of this panel's
-// columns, which are applied to column j and to the diagonal as they are
-// needed).  Step j picks the largest remaining diagonal, swaps rows and
-// columns j and p of the whole matrix (and perm), and forms column j of L.
-// rk[mat]: columns formed (n unless the factorisation stopped); dtop[mat]: the first pivot.
-__global__ __launch_bounds__(CT) void pchol_panel_kernel(double *K, int n, int j0, int nb, int *perm,
-                                                        int *status, int *rk, double *dtop, double tol) {
-    __shared__ double dd[1024];
-    __shared__ double rowj[CB];
-    __shared__ double rv[CT / 64];
-    __shared__ int ri[CT / 64];
-    __shared__ int piv;
-    __shared__ double dpiv;
-    __shared__ double d0;
-    __shared__ int stop;
-    const int mat = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
-    if (rk[mat] < n || status[mat]) return;   // stopped in an earlier panel
-    double *A = K + (size_t)mat * n * n;
+// Pivoted Cholesky without row or column exchanges: X = P L is formed in the
+// original row order.  S (overwritten) holds the Schur complement
+// K - X[:, :j0] X[:, :j0]^T in original indices, brought up to date after each
+// panel of PCW columns by one GEMM over the whole matrix.  Thread i keeps row i
+// of the panel's columns in registers.  Column j takes the unchosen index p with
+// the largest remaining diagonal d_p (ties: lowest index), reads row p of S
+// (contiguous), and sets x_i = (S[p, i] - sum over the panel's earlier columns
+// k of X[i, k] X[p, k]) / sqrt(d_p), with x_p = sqrt(d_p) and x = 0 at indices
+// chosen before; then d_i -= x_i^2.
+constexpr int PCW = 24;     // panel width (the row, 2 * PCW registers, fits 1024 threads)
+constexpr int PCT = 1024;   // threads: one per row (n <= 1024)
+
+// rk[mat]: columns formed (n unless the factorisation stopped); dtop[mat]: the
+// first pivot; perm[mat][j]: the index chosen for column j.
+__global__ __launch_bounds__(PCT) void pchol_panel_kernel(double *S, int n, int j0, int nb, int *perm,
+                                                         int *status, int *rk, double *dtop, double tol,
+                                                         double *X) {
+    __shared__ unsigned char chosen[PCT];
+    __shared__ double pv[PCT / 64];
+    __shared__ int pi[PCT / 64];
+    __shared__ double rowp[PCW];
+    const int mat = blockIdx.x, i = threadIdx.x, lane = i & 63, w = i >> 6;
+    if (rk[mat] < n || status[mat]) return;   // stopped in an earlier panel (uniform)
+    const double *Sm = S + (size_t)mat * n * n;
+    double *Xm = X + (size_t)mat * n * n;
     int *pm = perm + (size_t)mat * n;
-    if (t == 0) d0 = j0 > 0 ? dtop[mat] : 0.0;
-    // diagonal of the trailing matrix, corrected for nothing yet in this panel
-    for (int i = j0 + t; i < n; i += CT) dd[i] = A[(size_t)i * n + i];
+    chosen[i] = 0;
     __syncthreads();
-    for (int j = j0; j < j0 + nb; ++j) {
-        // argmax of dd[j:] (ties: lowest index)
-        double bv = -1.0;
-        int bi = j;
-        for (int i = j + t; i < n; i += CT)
-            if (dd[i] > bv) { bv = dd[i]; bi = i; }
+    for (int k = i; k < j0; k += PCT) chosen[pm[k]] = 1;
+    __syncthreads();
+    bool mine = i >= n || chosen[i];   // row i already has its pivot (or is padding)
+    double dd = mine ? 0.0 : Sm[(size_t)i * n + i];
+    double d0 = j0 > 0 ? dtop[mat] : 0.0;
+    double xr[PCW];
+#pragma unroll
+    for (int k = 0; k < PCW; ++k) xr[k] = 0.0;
+    // xr[k] = 0 for the panel's columns not formed yet, so every step runs the
+    // full-width dot product and all register indices are compile-time constants
+    for (int jj = 0; jj < nb; ++jj) {
+        // argmax over the unchosen rows; NaN never wins
+        double bv = (mine || !(dd == dd)) ? -INFINITY : dd;
+        int bi = mine ? PCT : i;
         for (int o = 32; o > 0; o >>= 1) {
             const double ov = __shfl_xor(bv, o, 64);
             const int oi = __shfl_xor(bi, o, 64);
-            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-        }
-        if (lane == 0) { rv[w] = bv; ri[w] = bi; }
-        __syncthreads();
-        if (t == 0) {
-            double v = rv[0];
-            int id = ri[0];
-            for (int x = 1; x < CT / 64; ++x)
-                if (rv[x] > v || (rv[x] == v && ri[x] < id)) { v = rv[x]; id = ri[x]; }
-            piv = id;
-            dpiv = v;
-            if (j == 0) {
-                d0 = v;
-                dtop[mat] = v;
+            if (ov > bv || (ov == bv && oi < bi)) {
+                bv = ov;
+                bi = oi;
             }
-            int st = 0;
-            if (!isfinite(v))
-                st = 1;
-            else if (tol > 0.0 ? v <= tol * d0 : !(v > 0.0))
-                st = tol > 0.0 ? 2 : 1;
-            if (st == 1) status[mat] = 1;   // the caller falls back
-            if (st == 2) rk[mat] = j;       // rank j: columns j.. stay zero
-            stop = st;
+        }
+        if (lane == 0) {
+            pv[w] = bv;
+            pi[w] = bi;
         }
         __syncthreads();
-        if (stop) return;   // uniform
-        const int p = piv;
-        if (p != j) {
-            for (int c = t; c < n; c += CT) {
-                const double x = A[(size_t)j * n + c];
-                A[(size_t)j * n + c] = A[(size_t)p * n + c];
-                A[(size_t)p * n + c] = x;
+        double v = pv[0];
+        int p = pi[0];
+        for (int x = 1; x < PCT / 64; ++x) {
+            const double ov = pv[x];
+            const int oi = pi[x];
+            if (ov > v || (ov == v && oi < p)) {
+                v = ov;
+                p = oi;
             }
-            __syncthreads();
-            for (int r = t; r < n; r += CT) {
-                const double x = A[(size_t)r * n + j];
-                A[(size_t)r * n + j] = A[(size_t)r * n + p];
-                A[(size_t)r * n + p] = x;
-            }
-            if (t == 0) {
-                const double x = dd[j];
-                dd[j] = dd[p];
-                dd[p] = x;
-                const int y = pm[j];
-                pm[j] = pm[p];
-                pm[p] = y;
-            }
-            __syncthreads();
         }
-        // row j of this panel's earlier columns
-        if (t < j - j0) rowj[t] = A[(size_t)j * n + j0 + t];
-        __syncthreads();
-        const double ljj = sqrt(dd[j]);
-        if (t == 0) A[(size_t)j * n + j] = ljj;
-        for (int i = j + 1 + t; i < n; i += CT) {
-            double a = A[(size_t)i * n + j];
-            const double *li = A + (size_t)i * n + j0;
-            for (int k = 0; k < j - j0; ++k) a -= li[k] * rowj[k];
-            a /= ljj;
-            A[(size_t)i * n + j] = a;
-            dd[i] -= a * a;
+        if (j0 + jj == 0) d0 = v;
+        // every thread reaches the same verdict from the same LDS values
+        int stop = 0;
+        if (!isfinite(v) || p >= n)
+            stop = 1;
+        else if (tol > 0.0 ? v <= tol * d0 : !(v > 0.0))
+            stop = tol > 0.0 ? 2 : 1;
+        if (stop) {
+            if (i == 0) {
+                if (stop == 1) status[mat] = 1;   // the caller falls back
+                else rk[mat] = j0 + jj;           // rank j0 + jj: columns from here on stay zero
+            }
+            break;
         }
+        if (i == p) {
+#pragma unroll
+            for (int k = 0; k < PCW; ++k) rowp[k] = xr[k];
+        }
+        if (i == 0) pm[j0 + jj] = p;
         __syncthreads();
+        if (i < n) {
+            const double ljj = sqrt(v);
+            double a = Sm[(size_t)p * n + i];
+#pragma unroll
+            for (int k = 0; k < PCW; ++k) a -= xr[k] * rowp[k];
+            const double x = i == p ? ljj : (mine ? 0.0 : a / ljj);
+#pragma unroll
+            for (int k = 0; k < PCW; ++k) xr[k] = k == jj ? x : xr[k];
+            if (i == p) mine = true;
+            if (!mine) dd -= x * x;
+        }
+    }
+    if (j0 == 0 && i == 0) dtop[mat] = d0;
+    if (i < n) {
+#pragma unroll
+        for (int k = 0; k < PCW; ++k)
+            if (k < nb) Xm[(size_t)i * n + j0 + k] = xr[k];
     }
 }
 
@@ -188,16 +194,6 @@ __global__ void perm_init_kernel(int *perm, int *rk, int *status, int n, int cou
             rk[e] = n;
             status[e] = 0;
         }
-    }
-}
-
-// X[perm[i], :] = L[i, :] (K = X X^T with X = P L)
-__global__ void unpermute_rows_kernel(const double *L, const int *perm, int n, int count, double *X) {
-    const long tot = (long)count * n * n;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
-        const long mat = e / ((long)n * n), rem = e % ((long)n * n);
-        const int i = (int)(rem / n), c = (int)(rem % n);
-        X[mat * n * n + (long)perm[mat * n + i] * n + c] = L[e];
     }
 }
 
@@ -225,25 +221,24 @@ bool pivoted_cholesky_batched(double *K, int count, int n, double *X, int *iws, 
     TRG_REQUIRE(reinterpret_cast<uintptr_t>(iws) % alignof(double) == 0, -1, "pivoted Cholesky: iws not 8-aligned");
     double *dtop = reinterpret_cast<double *>(iws);
     int *status = iws + 2 * count, *rk = status + count, *perm = rk + count;
-    const unsigned gb = (unsigned)std::min<size_t>(((size_t)count * n * n + 255) / 256, 65536);
+    const unsigned gb = (unsigned)std::min<size_t>(((size_t)count * n + 255) / 256, 65536);
     hipLaunchKernelGGL(perm_init_kernel, dim3(gb), dim3(256), 0, st, perm, rk, status, n, count);
-    for (int j0 = 0; j0 < n; j0 += CB) {
-        const int nb = std::min(CB, n - j0), rows = n - j0 - nb;
-        hipLaunchKernelGGL(pchol_panel_kernel, dim3(count), dim3(CT), 0, st, K, n, j0, nb, perm, status, rk, dtop,
-                           tol);
+    TRG_HIP_CHECK(hipMemsetAsync(X, 0, sizeof(double) * count * n * n, st));
+    for (int j0 = 0; j0 < n; j0 += PCW) {
+        const int nb = std::min(PCW, n - j0);
+        hipLaunchKernelGGL(pchol_panel_kernel, dim3(count), dim3(PCT), 0, st, K, n, j0, nb, perm, status, rk, dtop,
+                           tol, X);
         TRG_HIP_CHECK(hipGetLastError());
-        if (rows == 0) break;
+        if (j0 + nb == n) break;
+        // Schur complement: K -= X[:, j0:j0+nb] X[:, j0:j0+nb]^T
         GemmArgs h{};
-        h.M = rows; h.N = rows; h.K = nb; h.batch = count;
-        h.A = K + (size_t)(j0 + nb) * n + j0; h.sAr = n; h.sAk = 1; h.sAb = (long)n * n;
-        h.B = K + (size_t)(j0 + nb) * n + j0; h.sBk = 1; h.sBn = n; h.sBb = (long)n * n;
-        h.C = K + (size_t)(j0 + nb) * n + j0 + nb; h.sCr = n; h.sCn = 1; h.sCb = (long)n * n;
+        h.M = n; h.N = n; h.K = nb; h.batch = count;
+        h.A = X + j0; h.sAr = n; h.sAk = 1; h.sAb = (long)n * n;
+        h.B = X + j0; h.sBk = 1; h.sBn = n; h.sBb = (long)n * n;
+        h.C = K; h.sCr = n; h.sCn = 1; h.sCb = (long)n * n;
         h.alpha = -1.0; h.beta = 1.0;
         gemm(h, P_FP64, st);
     }
-    hipLaunchKernelGGL(zero_upper_kernel, dim3(gb), dim3(256), 0, st, K, n, count, rk);
-    hipLaunchKernelGGL(unpermute_rows_kernel, dim3(gb), dim3(256), 0, st, K, perm, n, count, X);
-    TRG_HIP_CHECK(hipGetLastError());
     std::vector<int> fl(2 * count);   // status, then rk
     TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), status, sizeof(int) * 2 * count, hipMemcpyDeviceToHost, st));
     TRG_HIP_CHECK(hipStreamSynchronize(st));
