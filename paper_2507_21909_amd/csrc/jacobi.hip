@@ -125,6 +125,10 @@ __global__ __launch_bounds__(NT) void full_kernel(JacobiBatch jb, int max_sweeps
 // round-robin played on slots: slots k and 15 - k meet, then the columns in
 // slots 1..15 move one slot on (register moves), so every register index is a
 // compile-time constant and 15 rounds bring each column back to its slot.
+// Only a sweep's first launch plays all 15 rounds, which covers the pairs
+// inside every block (each block sits in exactly one panel per launch); the
+// later launches play just the 8 rounds of pairs between the two blocks, so
+// a sweep visits each column pair once in about n sequential rounds.
 // The dot products are per-thread partial sums reduced across the wavefront by
 // a reduce-scatter butterfly and across the 4 wavefronts in LDS; the rotations
 // use the same formulas and threshold as rotate_pair.  The panel's rotations
@@ -149,9 +153,29 @@ __device__ inline void shift_slots(double (&u)[PW][ROWS], double (&vrow)[PW]) {
     vrow[1] = tmp;
 }
 
+// cross rounds: the columns in slots 8..15 move one slot on, cyclically
+template <int ROWS>
+__device__ inline void shift_cross(double (&u)[PW][ROWS], double (&vrow)[PW]) {
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) {
+        const double tmp = u[PW - 1][j];
+#pragma unroll
+        for (int c = PW - 1; c > PW / 2; --c) u[c][j] = u[c - 1][j];
+        u[PW / 2][j] = tmp;
+    }
+    const double tmp = vrow[PW - 1];
+#pragma unroll
+    for (int c = PW - 1; c > PW / 2; --c) vrow[c] = vrow[c - 1];
+    vrow[PW / 2] = tmp;
+}
+
+// cross != 0: only the 64 pairs between the two blocks, in 8 rounds (slot k
+// meets slot 15 - k while the second block's columns cycle through slots
+// 8..15); the pairs inside each block are left to the full rounds of the
+// sweep's first launch.
 template <int ROWS>
 __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r, double tol, int max_inner,
-                                                   int *flags) {
+                                                   int cross, int *flags) {
     const int k = blockIdx.x, mat = blockIdx.y, t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int I = player_at(nb, k, r), J = player_at(nb, nb - 1 - k, r);
     double *U = jb.ut + (long)mat * jb.strideU;
@@ -183,8 +207,9 @@ __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r
     __syncthreads();
     const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
     const int slot = (b5 ? 12 : 0) + (b4 ? 6 : 0) + (b3 ? 3 : 0);
+    const int nrounds = cross ? PW / 2 : PW - 1;
     for (int sw = 0; sw < max_inner; ++sw) {
-        for (int rr = 0; rr < PW - 1; ++rr) {
+        for (int rr = 0; rr < nrounds; ++rr) {
             double v[24];
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) {
@@ -264,7 +289,10 @@ __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r
                 vrow[kk] = c * x - s * y;
                 vrow[PW - 1 - kk] = s * x + c * y;
             }
-            shift_slots<ROWS>(u, vrow);
+            if (cross)
+                shift_cross<ROWS>(u, vrow);
+            else
+                shift_slots<ROWS>(u, vrow);
         }
         const int more = sweep_rot;
         __syncthreads();
@@ -459,13 +487,18 @@ int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *wo
         TRG_HIP_CHECK(hipMemsetAsync(flags_dev, 0, sizeof(int) * 2 * jb.count, st));
         if (panel) {
             dim3 grid(nbk / 2, jb.count);
+            // the first launch of a sweep also takes the pairs inside every block
             for (int r = 0; r < nbk - 1; ++r) {
+                const int cross = r > 0;
                 if (jb.m <= NT)
-                    hipLaunchKernelGGL(panel_kernel<1>, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, flags_dev);
+                    hipLaunchKernelGGL(panel_kernel<1>, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, cross,
+                                       flags_dev);
                 else if (jb.m <= 2 * NT)
-                    hipLaunchKernelGGL(panel_kernel<2>, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, flags_dev);
+                    hipLaunchKernelGGL(panel_kernel<2>, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, cross,
+                                       flags_dev);
                 else
-                    hipLaunchKernelGGL(panel_kernel<4>, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, flags_dev);
+                    hipLaunchKernelGGL(panel_kernel<4>, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, cross,
+                                       flags_dev);
             }
         } else {
             dim3 grid(cdiv(mm / 2, NT / 64), jb.count);
