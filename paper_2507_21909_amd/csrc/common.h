@@ -43,6 +43,11 @@ struct GemmArgs {
     double *C; long sCr, sCn, sCb;
     double alpha, beta;
     int inner; long sAi, sBi, sCi;
+    // optional two-level C index: with cR2 > 0 row r lands at
+    // (r / cR2) * sCr + (r % cR2) * sCr2 (likewise columns with cN2, sCn2),
+    // which writes C directly in a layout that interleaves the row and column
+    // legs; 0 keeps r * sCr (c * sCn)
+    int cR2, cN2; long sCr2, sCn2;
 };
 // ev0 / ev1 (optional): events stamped at the kernel's start and end
 void gemm(const GemmArgs &g, Prec prec, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

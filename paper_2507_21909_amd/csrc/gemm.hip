@@ -8,6 +8,10 @@
 // tile of C; its four wavefronts own 32x32 quadrants (2x2 MFMA tiles).  K is
 // staged through LDS in slabs of 16, K-major, and the next slab is fetched
 // into registers while the current one is multiplied.
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+
 #include <hip/hip_ext.h>
 
 #include "common.h"
@@ -40,6 +44,13 @@ __device__ inline void batch_ptrs(const GemmArgs &g, const double *&A, const dou
 // it then walks in groups of GM tile rows (column by column inside a group):
 // the group's A panels and the current B panel stay in that XCD's L2.
 constexpr int GM = 8;
+
+// element (r, c) of C relative to the batch entry's base
+__device__ inline long c_off(const GemmArgs &g, int r, int c) {
+    const long ro = g.cR2 > 0 ? (long)(r / g.cR2) * g.sCr + (long)(r % g.cR2) * g.sCr2 : (long)r * g.sCr;
+    const long co = g.cN2 > 0 ? (long)(c / g.cN2) * g.sCn + (long)(c % g.cN2) * g.sCn2 : (long)c * g.sCn;
+    return ro + co;
+}
 
 __device__ inline void tile_of(int &mt, int &nt) {
     const int nx = gridDim.x, ny = gridDim.y, T = nx * ny;
@@ -136,18 +147,141 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
                 int r = m0 + wr * (TM / 2) + i * 16 + (lane >> 4) + 4 * e;
                 int c = n0 + wc * (TM / 2) + j * 16 + (lane & 15);
                 if (r < g.M && c < g.N) {
-                    double *p = C + (long)r * g.sCr + (long)c * g.sCn;
+                    double *p = C + c_off(g, r, c);
                     double v = g.alpha * acc[i][j][e];
                     if (g.beta != 0.0) v += g.beta * *p;
                     *p = v;
                 }
             }
 }
+
+// The same 64 x 64 tile and K-16 slab as gemm_f64_kernel, for launches whose
+// tiles all lie inside C (M, N multiples of 64, K of 16) and whose operands
+// have a unit stride along one index with 16-byte aligned rows: each thread
+// fetches its 4 elements per operand and slab as two 16-byte loads from a
+// pointer that advances by one slab, with no per-element index arithmetic or
+// bounds checks.  AK1: A is k-contiguous (sAk = 1), else m-contiguous
+// (sAr = 1); BN1: B is n-contiguous (sBn = 1), else k-contiguous (sBk = 1).
+template <int TAG, bool AK1, bool BN1>
+__global__ __launch_bounds__(NT) void gemm_f64_vec_kernel(GemmArgs g) {
+    constexpr int TM = 64, KB = 16;
+    const double *A, *B;
+    double *C;
+    batch_ptrs(g, A, B, C);
+    int mt, nt;
+    tile_of(mt, nt);
+    const int m0 = mt * TM, n0 = nt * TM;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    __shared__ double As[KB][TM + LP];
+    __shared__ double Bs[KB][TM + LP];
+    // A: AK1 -> row t/4, k (t%4)*4 .. +3; else k t/16, rows (t%16)*4 .. +3
+    const int ar = AK1 ? t / 4 : (t % 16) * 4, ak = AK1 ? (t % 4) * 4 : t / 16;
+    // B: BN1 -> k t/16, cols (t%16)*4 .. +3; else col t/4, k (t%4)*4 .. +3
+    const int bc = BN1 ? (t % 16) * 4 : t / 4, bk = BN1 ? t / 16 : (t % 4) * 4;
+    const double *pa = A + (long)(m0 + ar) * g.sAr + (long)ak * g.sAk;
+    const double *pb = B + (long)bk * g.sBk + (long)(n0 + bc) * g.sBn;
+    const long da = (long)KB * g.sAk, db = (long)KB * g.sBk;   // one slab on
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 ra[2], rb[2];
+    auto load = [&]() {
+        ra[0] = *reinterpret_cast<const d2 *>(pa);
+        ra[1] = *reinterpret_cast<const d2 *>(pa + 2);
+        rb[0] = *reinterpret_cast<const d2 *>(pb);
+        rb[1] = *reinterpret_cast<const d2 *>(pb + 2);
+        pa += da;
+        pb += db;
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double x = ra[i / 2][i % 2], y = rb[i / 2][i % 2];
+            if (AK1) As[ak + i][ar] = x; else As[ak][ar + i] = x;
+            if (BN1) Bs[bk][bc + i] = y; else Bs[bk + i][bc] = y;
+        }
+    };
+    d4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    const int nk = g.K / KB;
+    load();
+    store();
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) load();
+#pragma unroll
+        for (int kk = 0; kk < KB; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            double af[2], bf[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) af[i] = As[kr][wr * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bf[j] = Bs[kr][wc * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            store();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = m0 + wr * 32 + i * 16 + (lane >> 4) + 4 * e;
+                const int c = n0 + wc * 32 + j * 16 + (lane & 15);
+                double *p = C + c_off(g, r, c);
+                double v = g.alpha * acc[i][j][e];
+                if (g.beta != 0.0) v += g.beta * *p;
+                *p = v;
+            }
+}
+
+// the vector kernel's preconditions; *ak1, *bn1 name its layout variant
+bool vec_ok(const GemmArgs &g, bool *ak1, bool *bn1) {
+    if (g.M % 64 || g.N % 64 || g.K % 16 || g.K == 0) return false;
+    auto even = [](long x) { return (x & 1) == 0; };
+    auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    if (!al16(g.A) || !al16(g.B)) return false;
+    if (!even(g.sAb) || !even(g.sBb) || (g.inner > 1 && (!even(g.sAi) || !even(g.sBi)))) return false;
+    if (g.sAk == 1 && even(g.sAr)) *ak1 = true;
+    else if (g.sAr == 1 && even(g.sAk)) *ak1 = false;
+    else return false;
+    if (g.sBn == 1 && even(g.sBk)) *bn1 = true;
+    else if (g.sBk == 1 && even(g.sBn)) *bn1 = false;
+    else return false;
+    return true;
+}
+
+template <int TAG>
+void launch_vec(bool ak1, bool bn1, dim3 grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const GemmArgs &h) {
+    auto kern = ak1 ? (bn1 ? gemm_f64_vec_kernel<TAG, true, true> : gemm_f64_vec_kernel<TAG, true, false>)
+                    : (bn1 ? gemm_f64_vec_kernel<TAG, false, true> : gemm_f64_vec_kernel<TAG, false, false>);
+    if (ev0) hipExtLaunchKernelGGL(kern, grid, dim3(NT), 0, st, ev0, ev1, 0, h);
+    else hipLaunchKernelGGL(kern, grid, dim3(NT), 0, st, h);
+}
 }  // namespace
 
 void gemm_f64(const GemmArgs &g, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
     const int inner = std::max(1, g.inner);
+    // shapes of every launch on stderr when TRG_GEMM_TRACE is set
+    static const bool trace = [] {
+        const char *e = getenv("TRG_GEMM_TRACE");
+        return e && *e && *e != '0';
+    }();
+    if (trace)
+        fprintf(stderr, "[gemm] M %d N %d K %ld batch %d inner %d sA %ld,%ld sB %ld,%ld sC %ld,%ld beta %g\n", g.M,
+                g.N, (long)g.K, g.batch, inner, g.sAr, g.sAk, g.sBk, g.sBn, g.sCr, g.sCn, g.beta);
     TRG_REQUIRE(inner == 1 || (long)g.batch * inner <= 65535, -6, "gemm: two-level batch too large");
     for (int b0 = 0; b0 < g.batch; b0 += 65535 / inner) {
         GemmArgs h = g;
@@ -162,6 +296,12 @@ void gemm_f64(const GemmArgs &g, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
                          (long)cdiv(h.N, 128) * cdiv(h.M, 128) * h.batch >= 256;
         const int tm = big ? 128 : 64;
         dim3 grid(cdiv(h.N, tm), cdiv(h.M, tm), h.batch * inner);
+        bool ak1 = false, bn1 = false;
+        if (!big && vec_ok(h, &ak1, &bn1)) {
+            if (ev0 && (long)g.batch * inner <= 65535) launch_vec<1>(ak1, bn1, grid, st, ev0, ev1, h);
+            else launch_vec<0>(ak1, bn1, grid, st, nullptr, nullptr, h);
+            continue;
+        }
         if (ev0 && (long)g.batch * inner <= 65535) {   // kernel start / end timestamps
             if (big) hipExtLaunchKernelGGL(gemm_f64_kernel<1, 128>, grid, dim3(NT), 0, st, ev0, ev1, 0, h);
             else hipExtLaunchKernelGGL(gemm_f64_kernel<1, 64>, grid, dim3(NT), 0, st, ev0, ev1, 0, h);
@@ -274,7 +414,7 @@ __global__ __launch_bounds__(NT) void gemm_f32_kernel(GemmArgs g) {
                 int r = m0 + wr * 32 + i * 16 + 4 * (lane >> 4) + e;
                 int c = n0 + wc * 32 + j * 16 + (lane & 15);
                 if (r < g.M && c < g.N) {
-                    double *p = C + (long)r * g.sCr + (long)c * g.sCn;
+                    double *p = C + c_off(g, r, c);
                     double v = g.alpha * dacc[i][j][e];
                     if (g.beta != 0.0) v += g.beta * *p;
                     *p = v;
@@ -390,7 +530,7 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(GemmArgs g) {
                 int r = m0 + wr * 32 + i * 16 + 4 * (lane >> 4) + e;
                 int c = n0 + wc * 32 + j * 16 + (lane & 15);
                 if (r < g.M && c < g.N) {
-                    double *p = C + (long)r * g.sCr + (long)c * g.sCn;
+                    double *p = C + c_off(g, r, c);
                     double v = g.alpha * dacc[i][j][e];
                     if (g.beta != 0.0) v += g.beta * *p;
                     *p = v;

@@ -30,6 +30,32 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// Rotation (c, s) that makes two columns with x.x = al, y.y = be, x.y = ga
+// orthogonal: t = tan(theta) the root of t^2 + 2 zeta t - 1 = 0 of smaller
+// magnitude, zeta = (be - al) / (2 ga), c = 1 / sqrt(1 + t^2), s = c t.
+// false (c = 1, s = 0) when the pair is orthogonal to tol already or a column
+// is (numerically) zero.
+__device__ inline bool jacobi_rotation(double al, double be, double ga, double tol, double &c, double &s) {
+    c = 1.0;
+    s = 0.0;
+    if (al < 1e-280 || be < 1e-280 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) return false;
+    const double zeta = (be - al) / (2.0 * ga);
+    const double az = fabs(zeta);
+    // sqrt(1 + zeta^2); past 1e150 the 1 is far below zeta's last bit
+    const double h = az < 1e150 ? sqrt(fma(az, az, 1.0)) : az;
+    const double t = (zeta < 0.0 ? -1.0 : 1.0) / (az + h);
+    c = 1.0 / sqrt(fma(t, t, 1.0));
+    s = c * t;
+    return true;
+}
+
+// lane l's value of v, as a wave-uniform value
+__device__ inline double read_lane(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
 // rotate pair k of round r of matrix (u, v); returns 1 if rotated, 2 if the
 // pair's dot products are not finite (the pair is then left alone), else 0
 __device__ int rotate_pair(double *u, double *v, int m, int n, int mm, int r, int k, double tol) {
@@ -49,10 +75,8 @@ __device__ int rotate_pair(double *u, double *v, int m, int n, int mm, int r, in
     be = wave_sum(be);
     ga = wave_sum(ga);
     if (!isfinite(al + be + ga)) return 2;
-    if (al < 1e-280 || be < 1e-280 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) return 0;
-    double zeta = (be - al) / (2.0 * ga);
-    double t = zeta == 0.0 ? 1.0 : copysign(1.0, zeta) / (fabs(zeta) + hypot(zeta, 1.0));
-    double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+    double c, s;
+    if (!jacobi_rotation(al, be, ga, tol, c, s)) return 0;
     for (int i = lane; i < m; i += 64) {
         double x = up[i], y = uq[i];
         up[i] = c * x - s * y;
@@ -130,11 +154,12 @@ __global__ __launch_bounds__(NT) void full_kernel(JacobiBatch jb, int max_sweeps
 // later launches play just the 8 rounds of pairs between the two blocks, so
 // a sweep visits each column pair once in about n sequential rounds.
 // The dot products are per-thread partial sums reduced across the wavefront by
-// a reduce-scatter butterfly and across the 4 wavefronts in LDS; the rotations
-// use the same formulas and threshold as rotate_pair.  The panel's rotations
-// are accumulated in a 16 x 16 matrix and applied to the 16 columns of V at
-// the end.  HBM sees each panel once per tournament round instead of once per
-// pair round, and a sweep needs nb - 1 launches instead of n - 1.
+// a reduce-scatter butterfly and across the 4 wavefronts in LDS; every
+// wavefront then computes the round's rotations itself (jacobi_rotation, as in
+// rotate_pair), so a round needs one barrier.  The panel's rotations are
+// accumulated in a 16 x 16 matrix and applied to the 16 columns of V at the
+// end.  HBM sees each panel once per tournament round instead of once per pair
+// round, and a sweep needs nb - 1 launches instead of n - 1.
 constexpr int PW = 16;
 constexpr int PANEL_INNER = 1;   // inner sweeps per panel and tournament round
 
@@ -173,7 +198,8 @@ __device__ inline void shift_cross(double (&u)[PW][ROWS], double (&vrow)[PW]) {
 // meets slot 15 - k while the second block's columns cycle through slots
 // 8..15); the pairs inside each block are left to the full rounds of the
 // sweep's first launch.
-template <int ROWS>
+// WV: V is accumulated (without it the 16 x 16 panel rotation is dead code)
+template <int ROWS, bool WV>
 __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r, double tol, int max_inner,
                                                    int cross, int *flags) {
     const int k = blockIdx.x, mat = blockIdx.y, t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -181,8 +207,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r
     double *U = jb.ut + (long)mat * jb.strideU;
     double *V = jb.vt ? jb.vt + (long)mat * jb.strideV : nullptr;
     const int m = jb.m, n = jb.n;
-    __shared__ double red[NT / 64][24];
-    __shared__ double rc[8], rs[8];
+    __shared__ double red[2][NT / 64][24];   // by round parity: one barrier per round
     __shared__ double vpan[PW][PW + 1];
     __shared__ int sweep_rot, total_rot, nonfinite;
 
@@ -208,6 +233,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r
     const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
     const int slot = (b5 ? 12 : 0) + (b4 ? 6 : 0) + (b3 ? 3 : 0);
     const int nrounds = cross ? PW / 2 : PW - 1;
+    int buf = 0;
     for (int sw = 0; sw < max_inner; ++sw) {
         for (int rr = 0; rr < nrounds; ++rr) {
             double v[24];
@@ -249,36 +275,33 @@ __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r
                 w3[i] += __shfl_xor(w3[i], 1, 64);
             }
             if ((lane & 7) == 0) {
-                red[w][slot] = w3[0];
-                red[w][slot + 1] = w3[1];
-                red[w][slot + 2] = w3[2];
+                red[buf][w][slot] = w3[0];
+                red[buf][w][slot + 1] = w3[1];
+                red[buf][w][slot + 2] = w3[2];
             }
             __syncthreads();
-            if (t < 8) {
+            // every wavefront computes the 8 rotations (lane kk: pair kk) from the
+            // same sums in the same order, so all rows see identical (c, s); the
+            // parity buffer keeps the next round's writes off this round's sums
+            double cl = 1.0, sl = 0.0;
+            if (lane < 8) {
                 double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
                 for (int x = 0; x < NT / 64; ++x) {
-                    al += red[x][3 * t];
-                    be += red[x][3 * t + 1];
-                    ga += red[x][3 * t + 2];
+                    al += red[buf][x][3 * lane];
+                    be += red[buf][x][3 * lane + 1];
+                    ga += red[buf][x][3 * lane + 2];
                 }
-                double c = 1.0, s = 0.0;
                 if (!isfinite(al + be + ga)) {
-                    nonfinite = 1;
-                } else if (!(al < 1e-280 || be < 1e-280 || fabs(ga) <= tol * sqrt(al) * sqrt(be))) {
-                    const double zeta = (be - al) / (2.0 * ga);
-                    const double tn = zeta == 0.0 ? 1.0 : copysign(1.0, zeta) / (fabs(zeta) + hypot(zeta, 1.0));
-                    c = 1.0 / sqrt(1.0 + tn * tn);
-                    s = c * tn;
-                    atomicAdd(&sweep_rot, 1);
+                    if (w == 0) nonfinite = 1;
+                } else if (jacobi_rotation(al, be, ga, tol, cl, sl)) {
+                    if (w == 0) atomicAdd(&sweep_rot, 1);
                 }
-                rc[t] = c;
-                rs[t] = s;
             }
-            __syncthreads();
+            buf ^= 1;
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) {
-                const double c = rc[kk], s = rs[kk];
+                const double c = read_lane(cl, kk), s = read_lane(sl, kk);
 #pragma unroll
                 for (int j = 0; j < ROWS; ++j) {
                     const double x = u[kk][j], y = u[PW - 1 - kk][j];
@@ -294,6 +317,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r
             else
                 shift_slots<ROWS>(u, vrow);
         }
+        __syncthreads();   // the last round's counts
         const int more = sweep_rot;
         __syncthreads();
         if (t == 0) {
@@ -318,12 +342,12 @@ __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r
             if (g < n && row < m) U[(long)g * m + row] = u[c][j];
         }
     }
+    if constexpr (!WV) return;
     if (t < PW) {
 #pragma unroll
         for (int c = 0; c < PW; ++c) vpan[t][c] = vrow[c];
     }
     __syncthreads();
-    if (!V) return;
     // V[:, panel] <- V[:, panel] * (panel rotation); thread t holds rows t + 256 j
     // (n <= m, so ROWS covers them); each thread reads its rows before writing them
     double vv[PW][ROWS];
@@ -488,17 +512,13 @@ int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *wo
         if (panel) {
             dim3 grid(nbk / 2, jb.count);
             // the first launch of a sweep also takes the pairs inside every block
+            const bool wv = jb.vt != nullptr;
+            auto kern = jb.m <= NT       ? (wv ? panel_kernel<1, true> : panel_kernel<1, false>)
+                        : jb.m <= 2 * NT ? (wv ? panel_kernel<2, true> : panel_kernel<2, false>)
+                                         : (wv ? panel_kernel<4, true> : panel_kernel<4, false>);
             for (int r = 0; r < nbk - 1; ++r) {
                 const int cross = r > 0;
-                if (jb.m <= NT)
-                    hipLaunchKernelGGL(panel_kernel<1>, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, cross,
-                                       flags_dev);
-                else if (jb.m <= 2 * NT)
-                    hipLaunchKernelGGL(panel_kernel<2>, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, cross,
-                                       flags_dev);
-                else
-                    hipLaunchKernelGGL(panel_kernel<4>, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, cross,
-                                       flags_dev);
+                hipLaunchKernelGGL(kern, grid, dim3(NT), 0, st, jb, nbk, r, tol, PANEL_INNER, cross, flags_dev);
             }
         } else {
             dim3 grid(cdiv(mm / 2, NT / 64), jb.count);

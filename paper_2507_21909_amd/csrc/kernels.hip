@@ -1,6 +1,9 @@
 // Layout, element-wise and bookkeeping kernels of the RG step.
 #include <cmath>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "common.h"
 
 namespace trg {
@@ -293,6 +296,17 @@ void permute(const double *src, double *dst, const std::vector<int> &dims, const
                 }
             }
         }
+    }
+    static const bool trace = [] {
+        const char *e = getenv("TRG_SHAPE_TRACE");
+        return e && *e && *e != '0';
+    }();
+    if (trace) {
+        fprintf(stderr, "[permute] total %ld dims", total);
+        for (int i = 0; i < nd; ++i) fprintf(stderr, " %d", dims[i]);
+        fprintf(stderr, " perm");
+        for (int i = 0; i < nd; ++i) fprintf(stderr, " %d", perm[i]);
+        fprintf(stderr, "\n");
     }
     PermArgs a{};
     a.nd = nd;

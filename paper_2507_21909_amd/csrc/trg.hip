@@ -686,7 +686,8 @@ void triad_isos(Step &T, const DT *grams, int d1, int d2, int rcap, DT *U) {
 // The two big contractions of makeMG (and, with G, H, N, of makeMH), slab by
 // slab over the first leg x of E (of H), as in the paper's GPU split of
 // Table I but within one device:
-//   K1: Z[x, u, c, v, g] = sum_{a, s} EM[x, u, c, a, s] F[a, s, v, g]
+//   K1: Z[x, u, v, c, g] = sum_{a, s} EM[x, u, c, a, s] F[a, s, v, g]
+//       (rows (u, c) and columns (v, g) of the GEMM written interleaved)
 //   K2: out[x, k, l, c, g] = sum_{u, v} T23[u, v, k, l] Z[x, u, v, c, g]
 // u, v are the triad bonds (kA, kX), c the squeezed t3 bond, g the bond-swap bond.
 DT coarse_half(Step &T, const DT &em, const DT &fp, const DT &t23) {
@@ -697,11 +698,10 @@ DT coarse_half(Step &T, const DT &em, const DT &fp, const DT &t23) {
     TRG_REQUIRE(fp.d[0] == Aa && fp.d[1] == Ss && t23.d[0] == U && t23.d[1] == V, -1, "coarse_half: shapes");
     DT out = talloc(c, {X, Kk, Ll, C, G});
     const long zslab = (long)U * C * V * G;
-    // slab group: keep one group's Z (and its permuted copy) near 1 GiB
+    // slab group: keep one group's Z near 1 GiB
     int xs = (int)std::max(1L, std::min<long>(X, (long)(134217728L / std::max(1L, zslab))));
     Arena::Mark mk = c.ar->mark();
-    DT z = talloc(c, {xs, U, C, V, G});
-    DT zp = talloc(c, {xs, U, V, C, G});
+    DT z = talloc(c, {xs, U, V, C, G});
     const long tiles2 = (long)((Kk * Ll + 63) / 64) * ((C * G + 63) / 64) * xs;
     int ks = 1;
     while (ks < 8 && tiles2 * ks < 1024 && (U * V) % (2 * ks) == 0 && (U * V) / (2 * ks) >= 2048) ks *= 2;
@@ -712,19 +712,19 @@ DT coarse_half(Step &T, const DT &em, const DT &fp, const DT &t23) {
         g.M = U * C; g.N = V * G; g.K = Aa * Ss; g.batch = nx;
         g.A = em.p + (long)x0 * U * C * Aa * Ss; g.sAr = (long)Aa * Ss; g.sAk = 1; g.sAb = (long)U * C * Aa * Ss;
         g.B = fp.p; g.sBk = (long)V * G; g.sBn = 1; g.sBb = 0;
-        g.C = z.p; g.sCr = (long)V * G; g.sCn = 1; g.sCb = zslab;
+        // rows (u, c) and columns (v, g) land in Z's [x, u, v, c, g] layout, K2's operand
+        g.C = z.p; g.sCb = zslab;
+        g.cR2 = C; g.sCr = (long)V * C * G; g.sCr2 = G;
+        g.cN2 = G; g.sCn = (long)C * G; g.sCn2 = 1;
         g.alpha = 1.0; g.beta = 0.0;
         timed_gemm(c, g, c.prec);
-        z.d[0] = nx;
-        zp.d[0] = nx;
-        permute(z.p, zp.p, z.d, {0, 1, 3, 2, 4}, c.st);
         // K2 has few output tiles (D^2 x D^2 per slab) over a long K = R^2: split K
         // so the launch fills the CUs, then add the slices in a fixed order
         const long mn = (long)Kk * Ll * C * G;
         GemmArgs h{};
         h.M = Kk * Ll; h.N = C * G; h.K = U * V; h.batch = nx;
         h.A = t23.p; h.sAr = 1; h.sAk = (long)Kk * Ll; h.sAb = 0;
-        h.B = zp.p; h.sBk = (long)C * G; h.sBn = 1; h.sBb = zslab;
+        h.B = z.p; h.sBk = (long)C * G; h.sBn = 1; h.sBb = zslab;
         h.alpha = 1.0; h.beta = 0.0;
         if (ks > 1) {
             h.K = U * V / ks;

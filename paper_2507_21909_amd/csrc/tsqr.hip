@@ -12,6 +12,9 @@
 #include <cmath>
 #include <mutex>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "common.h"
 
 namespace trg {
@@ -196,6 +199,11 @@ void launch_block_reg(int nb, const double *in, long rows, int n, double *rs, do
 void tsqr(const double *a, long m, int n, double *q, double *r, double *ws, hipStream_t st) {
     TRG_REQUIRE(n >= 1 && n <= 64, -6, "tsqr: n must be in [1, 64]");
     TRG_REQUIRE(m >= n, -6, "tsqr: needs m >= n");
+    static const bool trace = [] {
+        const char *e = getenv("TRG_SHAPE_TRACE");
+        return e && *e && *e != '0';
+    }();
+    if (trace) fprintf(stderr, "[tsqr] m %ld n %d\n", m, n);
     const int BR = RB;
     std::vector<Level> lv;
     double *p = ws;
