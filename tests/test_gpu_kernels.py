@@ -15,10 +15,10 @@ def _say(*a):
     sys.stdout.flush()
 
 
-# (5, 64, 64, 64), (2, 128, 192, 48), (1, 256, 64, 1024): every tile inside C and
-# K a multiple of 16, the vector-load kernel; the others the general one
+# (5, 64, 64, 64), (2, 128, 192, 64), (1, 256, 64, 1024): every tile inside C and
+# K a multiple of 32, the vector-load kernel; the others the general one
 @pytest.mark.parametrize("shape", [(1, 16, 16, 4), (3, 67, 45, 33), (2, 130, 70, 129), (1, 1, 200, 17),
-                                   (5, 64, 64, 64), (1, 300, 1, 7), (2, 128, 192, 48), (1, 256, 64, 1024)])
+                                   (5, 64, 64, 64), (1, 300, 1, 7), (2, 128, 192, 64), (1, 256, 64, 1024), (1, 64, 128, 48)])
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
 def test_gemm_f64(shape, ta, tb):
     batch, m, n, k = shape
