@@ -5,12 +5,14 @@
 // Level l splits its rows into blocks of 256 rows; one workgroup factors a
 // block with Householder reflections (LAPACK dlarfg / dlarf order), one row of
 // the block per thread held in registers, and writes the n x n R factor and
-// the explicit 256 x n thin Q (dorg2r order).  The stacked R factors are the
+// the explicit 256 x n thin Q (dorg2r order).  The reflectors wait in the
+// block's own rows of the Q output (each thread reads back only its row), so
+// the kernel needs no large LDS buffer and, at up to 256 registers per lane,
+// two blocks share a CU and hide each other's reduction latency.  The stacked R factors are the
 // next level's input; the last level (one block) fixes diag(R) >= 0.  Q is
 // then rebuilt top-down: Q_l[block b] = Q_l,b * Q_{l+1}[b*n:(b+1)*n, :], a
 // batched GEMM per level.
 #include <cmath>
-#include <mutex>
 
 #include <cstdio>
 #include <cstdlib>
@@ -28,10 +30,11 @@ constexpr int NT = 256;
 // butterfly across the wavefront, then the 4 wavefronts in LDS.
 constexpr int RB = 256;   // rows per block
 
-// one halving step of the reduce-scatter: CNT live values in v[0..CNT), the
-// partner (lane ^ off) keeps the other half; all indices compile-time
+// reduce-scatter halving steps: CNT live values in v[0..CNT); the partner
+// (lane ^ off) keeps the other half; all indices compile-time.  The first step
+// (off 32) is wg_sum's own, so v holds NC / 2 values
 template <int NC, int CNT>
-__device__ inline void halve(double (&v)[NC], int lane, int &idx) {
+__device__ inline void halve_rest(double (&v)[NC / 2], int lane, int &idx) {
     if constexpr (CNT > 1) {
         constexpr int half = CNT / 2, off = 32 * CNT / NC;
         const bool hi = lane & off;
@@ -41,16 +44,26 @@ __device__ inline void halve(double (&v)[NC], int lane, int &idx) {
             v[i] = keep + __shfl_xor(send, off, 64);
         }
         idx += hi ? half : 0;
-        halve<NC, half>(v, lane, idx);
+        halve_rest<NC, half>(v, lane, idx);
     }
 }
 
-// sum over the workgroup of v[0..NC) (per thread); result in out[0..NC) (LDS)
+// sum over the workgroup of s * x[0..NC) (per thread); result in out[0..NC)
+// (LDS).  The first halving step reads s * x directly, so the products never
+// take NC registers of their own.
 template <int NC>
-__device__ inline void wg_sum(double (&v)[NC], double (*red)[NC], double *out) {
+__device__ inline void wg_sum(const double (&x)[NC], double s, double (*red)[NC], double *out) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int idx = 0;
-    halve<NC, NC>(v, lane, idx);
+    constexpr int H = NC / 2;
+    const bool hi = lane & 32;
+    double v[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const double send = s * (hi ? x[i] : x[H + i]), keep = s * (hi ? x[H + i] : x[i]);
+        v[i] = keep + __shfl_xor(send, 32, 64);
+    }
+    int idx = hi ? H : 0;
+    halve_rest<NC, H>(v, lane, idx);
     // v[0] holds value idx summed over the lanes that differ in the top bits;
     // finish over the low 64 / NC lanes
 #pragma unroll
@@ -63,9 +76,8 @@ __device__ inline void wg_sum(double (&v)[NC], double (*red)[NC], double *out) {
 }
 
 template <int NC>
-__global__ __launch_bounds__(NT) void qr_block_reg_kernel(const double *a_in, long rows, int n, double *rout,
-                                                          double *qout, int final_level) {
-    extern __shared__ double vl[];            // RB x NC: Householder vectors (below diag) and R
+__global__ __launch_bounds__(NT, 2) void qr_block_reg_kernel(const double *a_in, long rows, int n, double *rout,
+                                                             double *qout, int final_level) {
     __shared__ double red[4][NC];
     __shared__ double wsum[NC], taus[NC], dsg[NC];
     __shared__ double ab[2];
@@ -111,24 +123,25 @@ __global__ __launch_bounds__(NT) void qr_block_reg_kernel(const double *a_in, lo
 #pragma unroll
         for (int c = 0; c < NC; ++c) a[c] = c == j ? newx : a[c];
         if (tau == 0.0) continue;   // uniform
-        double p[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) p[c] = vt * a[c];
-        wg_sum<NC>(p, red, wsum);
+        wg_sum<NC>(a, vt, red, wsum);
         const double tv = tau * vt;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             if (c > j) a[c] -= tv * wsum[c];
     }
-    // R rows (thread t < n owns row t) with the final level's sign; vectors to LDS
+    // R rows (thread t < n owns row t) with the final level's sign
     if (t < n) {
         double d = 0.0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) d = c == t ? a[c] : d;
         dsg[t] = (final_level && d < 0.0) ? -1.0 : 1.0;
     }
+    // reflectors (row t of V, below the diagonal) into this thread's own row of
+    // the Q output, read back by the same thread below
+    double *qo = qout + (long)b * RB * n;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) vl[t * NC + c] = a[c];
+    for (int c = 0; c < NC; ++c)
+        if (c < n) qo[(long)t * n + c] = a[c];
     __syncthreads();
     if (t < n) {
         const double sg = dsg[t];
@@ -140,19 +153,20 @@ __global__ __launch_bounds__(NT) void qr_block_reg_kernel(const double *a_in, lo
     double q[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) q[c] = (t == c && c < n) ? 1.0 : 0.0;
+    // v of the next column is fetched one step ahead (barriers wait on LDS only,
+    // so the load overlaps the current step's reductions)
+    double vnext = t > n - 1 ? qo[(long)t * n + n - 1] : 0.0;
     for (int j = n - 1; j >= 0; --j) {
+        const double vcur = vnext;
+        if (j > 0) vnext = t > j - 1 ? qo[(long)t * n + j - 1] : 0.0;
         const double tau = taus[j];
         if (tau == 0.0) continue;   // uniform
-        const double vt = t == j ? 1.0 : (t > j ? vl[t * NC + j] : 0.0);
-        double p[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) p[c] = vt * q[c];
-        wg_sum<NC>(p, red, wsum);
+        const double vt = t == j ? 1.0 : (t > j ? vcur : 0.0);
+        wg_sum<NC>(q, vt, red, wsum);
         const double tv = tau * vt;
 #pragma unroll
         for (int c = 0; c < NC; ++c) q[c] -= tv * wsum[c];
     }
-    double *qo = qout + (long)b * RB * n;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
         if (c < n) qo[(long)t * n + c] = q[c] * dsg[c];
@@ -185,14 +199,7 @@ size_t tsqr_ws_doubles(long m, int n) {
 namespace {
 template <int NC>
 void launch_block_reg(int nb, const double *in, long rows, int n, double *rs, double *q, bool fin, hipStream_t st) {
-    const size_t lds = (size_t)RB * NC * sizeof(double);
-    static std::once_flag attr;
-    std::call_once(attr, [lds] {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(qr_block_reg_kernel<NC>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-            (void)hipGetLastError();
-    });
-    hipLaunchKernelGGL(qr_block_reg_kernel<NC>, dim3(nb), dim3(NT), lds, st, in, rows, n, rs, q, fin ? 1 : 0);
+    hipLaunchKernelGGL(qr_block_reg_kernel<NC>, dim3(nb), dim3(NT), 0, st, in, rows, n, rs, q, fin ? 1 : 0);
 }
 }  // namespace
 
