@@ -49,6 +49,14 @@ __device__ inline bool jacobi_rotation(double al, double be, double ga, double t
     return true;
 }
 
+// v from the lane that DPP control CTRL selects (all lanes active)
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 // lane l's value of v, as a wave-uniform value
 __device__ inline double read_lane(double v, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -218,7 +226,9 @@ __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
             const int row = t + NT * j;
-            u[c][j] = (g < n && row < m) ? U[(long)g * m + row] : 0.0;
+            // nontemporal: a panel is read and written once per launch and the
+            // next launch takes it on another XCD, so it gains nothing in L2
+            u[c][j] = (g < n && row < m) ? __builtin_nontemporal_load(&U[(long)g * m + row]) : 0.0;
         }
     }
     double vrow[PW];
@@ -263,16 +273,19 @@ __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r
                 const double send = b4 ? w12[i] : w12[6 + i], keep = b4 ? w12[6 + i] : w12[i];
                 w6[i] = keep + __shfl_xor(send, 16, 64);
             }
+            // inside 16-lane rows the partners come from DPP: row_mirror pairs
+            // lane l with l ^ 15 (opposite bit 3), then half-mirror (l ^ 7) and
+            // the quad permutations l ^ 2, l ^ 1 finish the sums over 8 lanes
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const double send = b3 ? w6[i] : w6[3 + i], keep = b3 ? w6[3 + i] : w6[i];
-                w3[i] = keep + __shfl_xor(send, 8, 64);
+                w3[i] = keep + dpp_d<0x140>(send);
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                w3[i] += __shfl_xor(w3[i], 4, 64);
-                w3[i] += __shfl_xor(w3[i], 2, 64);
-                w3[i] += __shfl_xor(w3[i], 1, 64);
+                w3[i] += dpp_d<0x141>(w3[i]);
+                w3[i] += dpp_d<0x4E>(w3[i]);
+                w3[i] += dpp_d<0xB1>(w3[i]);
             }
             if ((lane & 7) == 0) {
                 red[buf][w][slot] = w3[0];
@@ -339,7 +352,9 @@ __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
             const int row = t + NT * j;
-            if (g < n && row < m) U[(long)g * m + row] = u[c][j];
+            if (g < n && row < m) {
+                __builtin_nontemporal_store(u[c][j], &U[(long)g * m + row]);
+            }
         }
     }
     if constexpr (!WV) return;
