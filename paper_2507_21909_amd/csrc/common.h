@@ -76,13 +76,16 @@ void zero_tail_cols(double *a, long rows, int cols, long ld, const int *kept_dev
                     hipStream_t st);
 // sign convention: sg[j] = sign(sum_i w(i) Q[i,j]); row multi-index decoded from
 // `dims` (row-major over the GPU layout), each leg contributing idx * pw[leg].
+// ws: weight_ws_doubles(rows, cols, 1) doubles of scratch.
 void sign_vector(const double *q, long rows, int cols, long ld, const std::vector<int> &dims,
-                 const std::vector<double> &pw, double *sg, hipStream_t st);
+                 const std::vector<double> &pw, double *sg, double *ws, hipStream_t st);
+// scratch for the weight sums of `cols` columns of `rows` rows with L weights
+size_t weight_ws_doubles(long rows, int cols, int L);
 // Canonical basis within multiplets: rot (cols x cols, block diagonal) such that
 // q rot has, in every group of the first *k_dev values closer than tau * vals[0],
 // the columns Q_m Q_z with Q_z the Q factor of Q_m^T W (fixed weights w_l of the
-// row multi-index).  z_work holds cols * 16 doubles; status gets 2 if a group
-// is larger than 16.
+// row multi-index).  z_work holds weight_ws_doubles(rows, cols, 16) doubles;
+// status gets 2 if a group is larger than 16.
 void canonical_rotation(const double *q, long rows, int cols, long ld, const std::vector<int> &dims,
                         const std::vector<double> &pw, const double *vals, const int *k_dev, double tau,
                         double *z_work, double *rot, int *status, hipStream_t st);

@@ -96,33 +96,6 @@ struct SignArgs {
     double pw[MAXD];
 };
 
-// one workgroup per column; w(i) = 0.5 + frac(g (1 + sum_l idx_l pw_l))
-__global__ void sign_kernel(const double *q, long rows, int cols, long ld, SignArgs a, double *sg) {
-    const double golden = 0.6180339887498949;
-    int j = blockIdx.x;
-    double acc = 0.0;
-    for (long r = threadIdx.x; r < rows; r += blockDim.x) {
-        long rem = r;
-        double code = 0.0;
-        for (int d = a.nd - 1; d >= 0; --d) {
-            long qd = rem / a.dd[d];
-            code += (double)(rem - qd * a.dd[d]) * a.pw[d];
-            rem = qd;
-        }
-        double x = golden * (1.0 + code);
-        double wgt = 0.5 + (x - floor(x));
-        acc += wgt * q[r * ld + j];
-    }
-    __shared__ double red[256];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) sg[j] = red[0] < 0.0 ? -1.0 : 1.0;
-}
-
 __global__ void scale_cols_kernel(double *a, long rows, int cols, long ld, const double *sg) {
     long n = rows * (long)cols;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -178,13 +151,24 @@ __global__ void sketch_kernel(double *out, SketchArgs a) {
     }
 }
 
-// Z[j][l] = sum_i Q[i, j] w_l(i), w_l(i) = 0.5 + frac(g (1 + code(i)) + l (sqrt 2 - 1)), l < L
-__global__ void weights_dot_kernel(const double *q, long rows, int cols, long ld, SignArgs a, int L, double *z) {
+// Z[j][l] = sum_i Q[i, j] w_l(i), w_l(i) = 0.5 + frac(g (1 + code(i)) + l (sqrt 2 - 1)),
+// l < L <= 16, with code(i) = sum_d idx_d(i) pw_d over the row multi-index.
+// First pass: workgroup (x, y) takes 64 columns and the y-th chunk of rpb rows;
+// each wavefront reads whole 64-column row segments (coalesced), every 4th row
+// of the chunk, and the 4 wavefronts' sums are added in a fixed order into
+// part[(y * cols + j) * L + l].  Second pass: Z = the chunk partials added in
+// chunk order (and, with sg, the sign of Z[j][0]).  Both orders are fixed, so
+// the sums are the same bits on every run.
+__global__ __launch_bounds__(256) void weights_partial_kernel(const double *q, long rows, int cols, long ld,
+                                                              SignArgs a, int L, long rpb, double *part) {
     const double golden = 0.6180339887498949, c2 = 0.41421356237309515;
-    int j = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
+    const long r0 = (long)blockIdx.y * rpb, r1 = r0 + rpb < rows ? r0 + rpb : rows;
     double acc[16];
+#pragma unroll
     for (int l = 0; l < 16; ++l) acc[l] = 0.0;
-    for (long r = threadIdx.x; r < rows; r += blockDim.x) {
+    for (long r = r0 + w; r < r1; r += 4) {
         long rem = r;
         double code = 0.0;
         for (int d = a.nd - 1; d >= 0; --d) {
@@ -192,24 +176,33 @@ __global__ void weights_dot_kernel(const double *q, long rows, int cols, long ld
             code += (double)(rem - qd * a.dd[d]) * a.pw[d];
             rem = qd;
         }
-        double x = golden * (1.0 + code);
-        double v = q[r * ld + j];
-        for (int l = 0; l < L; ++l) {
-            double y = x + l * c2;
-            acc[l] += (0.5 + (y - floor(y))) * v;
-        }
+        const double x = golden * (1.0 + code);
+        const double v = j < cols ? q[r * ld + j] : 0.0;
+#pragma unroll
+        for (int l = 0; l < 16; ++l)
+            if (l < L) {
+                const double y = x + l * c2;
+                acc[l] += (0.5 + (y - floor(y))) * v;
+            }
     }
-    __shared__ double red[256];
-    for (int l = 0; l < L; ++l) {
-        red[threadIdx.x] = acc[l];
-        __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) z[(long)j * L + l] = red[0];
-        __syncthreads();
-    }
+    __shared__ double red[4][64][17];
+#pragma unroll
+    for (int l = 0; l < 16; ++l)
+        if (l < L) red[w][lane][l] = acc[l];
+    __syncthreads();
+    if (w == 0 && j < cols)
+        for (int l = 0; l < L; ++l)
+            part[((long)blockIdx.y * cols + j) * L + l] =
+                ((red[0][lane][l] + red[1][lane][l]) + red[2][lane][l]) + red[3][lane][l];
+}
+
+__global__ void weights_final_kernel(const double *part, int nchunk, int cols, int L, double *z, double *sg) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;   // j * L + l
+    if (i >= cols * L) return;
+    double acc = 0.0;
+    for (int b = 0; b < nchunk; ++b) acc += part[(long)b * cols * L + i];
+    z[i] = acc;
+    if (sg) sg[i] = acc < 0.0 ? -1.0 : 1.0;   // L == 1
 }
 
 // Block-diagonal canonical rotation (n x n): identity, except on each multiplet
@@ -369,8 +362,38 @@ void zero_tail_cols(double *a, long rows, int cols, long ld, const int *kept_dev
     TRG_HIP_CHECK(hipGetLastError());
 }
 
+namespace {
+// rows per chunk of the weight sums: at most 512 chunks, at least 256 rows each
+long weight_rpb(long rows) {
+    long r = (rows + 511) / 512;
+    r = (r + 3) / 4 * 4;
+    return r < 256 ? 256 : r;
+}
+
+}  // namespace
+
+size_t weight_ws_doubles(long rows, int cols, int L) {
+    const long rpb = weight_rpb(rows), nchunk = (rows + rpb - 1) / rpb;
+    return (size_t)(nchunk + 1) * cols * L + 16;
+}
+
+namespace {
+// Z (cols x L) into z, the chunk partials in ws (weight_ws_doubles)
+void weight_sums(const double *q, long rows, int cols, long ld, const SignArgs &a, int L, double *ws, double *z,
+                 double *sg, hipStream_t st) {
+    const long rpb = weight_rpb(rows);
+    const int nchunk = (int)((rows + rpb - 1) / rpb);
+    TRG_REQUIRE(L >= 1 && L <= 16, -1, "weight sums: L out of range");
+    dim3 grid((cols + 63) / 64, nchunk);
+    hipLaunchKernelGGL(weights_partial_kernel, grid, dim3(256), 0, st, q, rows, cols, ld, a, L, rpb, ws);
+    hipLaunchKernelGGL(weights_final_kernel, dim3((cols * L + 255) / 256), dim3(256), 0, st, ws, nchunk, cols, L,
+                       z, sg);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+}  // namespace
+
 void sign_vector(const double *q, long rows, int cols, long ld, const std::vector<int> &dims,
-                 const std::vector<double> &pw, double *sg, hipStream_t st) {
+                 const std::vector<double> &pw, double *sg, double *ws, hipStream_t st) {
     SignArgs a{};
     a.nd = (int)dims.size();
     TRG_REQUIRE(a.nd <= MAXD && pw.size() == dims.size(), -1, "sign_vector: bad dims");
@@ -378,8 +401,8 @@ void sign_vector(const double *q, long rows, int cols, long ld, const std::vecto
     for (int i = 0; i < a.nd; ++i) { a.dd[i] = dims[i]; a.pw[i] = pw[i]; prod *= dims[i]; }
     TRG_REQUIRE(prod == rows, -1, "sign_vector: dims do not match rows");
     if (cols == 0) return;
-    hipLaunchKernelGGL(sign_kernel, dim3(cols), dim3(256), 0, st, q, rows, cols, ld, a, sg);
-    TRG_HIP_CHECK(hipGetLastError());
+    const long rpb = weight_rpb(rows), nchunk = (rows + rpb - 1) / rpb;
+    weight_sums(q, rows, cols, ld, a, 1, ws, ws + nchunk * cols, sg, st);
 }
 
 void scale_cols(double *a, long rows, int cols, long ld, const double *sg, hipStream_t st) {
@@ -424,8 +447,9 @@ void canonical_rotation(const double *q, long rows, int cols, long ld, const std
     TRG_REQUIRE(prod == rows, -1, "canonical_rotation: dims do not match rows");
     if (cols == 0) return;
     const int L = 16;
-    hipLaunchKernelGGL(weights_dot_kernel, dim3(cols), dim3(256), 0, st, q, rows, cols, ld, a, L, z_work);
-    hipLaunchKernelGGL(canon_rot_kernel, dim3(1), dim3(64), 0, st, vals, cols, k_dev, tau, z_work, L, rot, status);
+    double *z = z_work, *part = z_work + (size_t)cols * L;
+    weight_sums(q, rows, cols, ld, a, L, part, z, nullptr, st);
+    hipLaunchKernelGGL(canon_rot_kernel, dim3(1), dim3(64), 0, st, vals, cols, k_dev, tau, z, L, rot, status);
     TRG_HIP_CHECK(hipGetLastError());
 }
 }  // namespace trg

@@ -260,7 +260,7 @@ Split resplit(Step &T, const std::vector<int> &order) {
     kept_count(s.p, chi, chi, 0.0, -1.0, kpos, c.st);           // number of s > 0
     std::vector<int> nd(S->dims.begin(), S->dims.end());
     DT rot = talloc(c, {chi, chi});
-    double *zw = c.ar->dalloc((size_t)chi * 16);
+    double *zw = c.ar->dalloc(weight_ws_doubles(F, chi, 16));
     canonical_rotation(A.p, F, chi, chi, nd, pow131(d), s.p, kpos, T.S->opt.tau_deg, zw, rot.p, S->dint, c.st);
     DT A2 = contract(c, A, "Fa", rot, "ab", "Fb");
     DT D2 = contract(c, Dm, "Fa", rot, "ab", "Fb");
@@ -348,7 +348,8 @@ Swap bond_swap(Step &T, const Split &sp) {
         std::vector<int> sd{chi};
         sd.insert(sd.end(), td.begin(), td.end());
         double *sg = c.ar->dalloc(gcap);
-        sign_vector(X.p, chi * I, gcap, gcap, sd, pow131((int)sd.size()), sg, c.st);
+        sign_vector(X.p, chi * I, gcap, gcap, sd, pow131((int)sd.size()), sg,
+                    c.ar->dalloc(weight_ws_doubles((long)chi * I, gcap, 1)), c.st);
         scale_cols(X.p, chi * I, gcap, gcap, sg, c.st);
         scale_cols(Y.p, chi * J, gcap, gcap, sg, c.st);
         o.X = X;
@@ -435,7 +436,7 @@ Swap bond_swap(Step &T, const Split &sp) {
     for (size_t i = 0; i < td.size(); ++i) { pw.push_back(mlt); mlt *= 131.0; }
     pw.push_back(1.0);
     double *sg = c.ar->dalloc(gcap);
-    sign_vector(ub.p, I * chi, gcap, gcap, sd, pw, sg, c.st);
+    sign_vector(ub.p, I * chi, gcap, gcap, sd, pw, sg, c.ar->dalloc(weight_ws_doubles((long)I * chi, gcap, 1)), c.st);
     scale_cols(ub.p, I * chi, gcap, gcap, sg, c.st);
     scale_cols(vb.p, J * chi, gcap, gcap, sg, c.st);
     ub.d = td;
@@ -569,7 +570,7 @@ void squeezers(Step &T, const double *kf, const double *kb, int cnt, int dt, int
         scale_axis(ud.p, ud.d, 1, is.p, 1, c.st);
         // canonical basis of the new leg within multiplets of S
         DT rot = talloc(c, {D, D});
-        double *zw = c.ar->dalloc((size_t)D * 16);
+        double *zw = c.ar->dalloc(weight_ws_doubles(n, D, 16));
         canonical_rotation(vd.p, n, D, D, {dt, db}, {1.0, 131.0}, si, kept, T.S->opt.tau_deg, zw, rot.p, S->dint, c.st);
         E[i] = contract(c, vd, "pk", rot, "kl", "pl");
         E[i].d = {dt, db, D};
@@ -677,7 +678,8 @@ void triad_isos(Step &T, const DT *grams, int d1, int d2, int rcap, DT *U) {
         col_slice(c, vec.p + i * nn, n, n, rcap, U[i].p);
         zero_tail_cols(U[i].p, n, rcap, rcap, kept, c.st);
         double *sg = c.ar->dalloc(rcap);
-        sign_vector(U[i].p, n, rcap, rcap, {d1, d2}, {1.0, 131.0}, sg, c.st);
+        sign_vector(U[i].p, n, rcap, rcap, {d1, d2}, {1.0, 131.0}, sg, c.ar->dalloc(weight_ws_doubles(n, rcap, 1)),
+                    c.st);
         scale_cols(U[i].p, n, rcap, rcap, sg, c.st);
         U[i].d = {d1, d2, rcap};
     }
