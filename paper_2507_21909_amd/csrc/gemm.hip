@@ -49,10 +49,31 @@ __device__ inline void batch_ptrs(const GemmArgs &g, const double *&A, const dou
 // the group's A panels and the current B panel stay in that XCD's L2.
 constexpr int GM = 8;
 
+// x / d and x % d, by shift and mask when d is a power of two (d > 0)
+__device__ inline void divmod(int x, int d, int &q, int &r) {
+    if ((d & (d - 1)) == 0) {
+        const int sh = __ffs(d) - 1;
+        q = x >> sh;
+        r = x & (d - 1);
+    } else {
+        q = x / d;
+        r = x - q * d;
+    }
+}
+
 // element (r, c) of C relative to the batch entry's base
 __device__ inline long c_off(const GemmArgs &g, int r, int c) {
-    const long ro = g.cR2 > 0 ? (long)(r / g.cR2) * g.sCr + (long)(r % g.cR2) * g.sCr2 : (long)r * g.sCr;
-    const long co = g.cN2 > 0 ? (long)(c / g.cN2) * g.sCn + (long)(c % g.cN2) * g.sCn2 : (long)c * g.sCn;
+    long ro = (long)r * g.sCr, co = (long)c * g.sCn;
+    if (g.cR2 > 0) {
+        int q, m;
+        divmod(r, g.cR2, q, m);
+        ro = (long)q * g.sCr + (long)m * g.sCr2;
+    }
+    if (g.cN2 > 0) {
+        int q, m;
+        divmod(c, g.cN2, q, m);
+        co = (long)q * g.sCn + (long)m * g.sCn2;
+    }
     return ro + co;
 }
 
