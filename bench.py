@@ -26,7 +26,7 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense MFMA TFLOP/s, M
 # HBM bytes per makeMG/makeMH launch (FETCH_SIZE + WRITE_SIZE from two rocprofv3
 # --pmc runs of this benchmark, each scaled by the counter's reading for a plain
 # 1 GiB copy) for the FP64 kernel at D = 32, r = 7; None for other settings.
-TRAFFIC = {}
+TRAFFIC = {("fp64", 32, 7): 5.30e9}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
 
 
