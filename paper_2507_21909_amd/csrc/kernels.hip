@@ -29,6 +29,47 @@ __global__ void permute_kernel(const double *__restrict__ src, double *__restric
     }
 }
 
+// General permutation whose destination's last axis is not the source's unit
+// stride axis: 32 x 32 tiles over dst axis ka (source stride 1) and dst axis
+// nd - 1, staged through LDS so that reads run along the source's unit stride
+// and writes along the destination's; block id = (batch, tile_b, tile_a) with
+// the batch over the other destination axes.  dst strides are row-major.
+__global__ __launch_bounds__(256) void permute_tiled_kernel(const double *__restrict__ src, double *__restrict__ dst,
+                                                            PermArgs a, int ka, long nta, long ntb) {
+    __shared__ double tile[32][33];
+    const int L = a.nd - 1, tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    long bid = blockIdx.x;
+    const long ta = bid % nta;
+    bid /= nta;
+    const long tb = bid % ntb;
+    long batch = bid / ntb;
+    // destination strides (row-major) and the batch's base offsets
+    long ostr[MAXD];
+    ostr[L] = 1;
+    for (int d = L - 1; d >= 0; --d) ostr[d] = ostr[d + 1] * a.dd[d + 1];
+    long in_base = 0, out_base = 0;
+    for (int d = L - 1; d >= 0; --d) {
+        if (d == ka) continue;
+        const long q = batch / a.dd[d];
+        const long idx = batch - q * a.dd[d];
+        in_base += idx * a.ss[d];
+        out_base += idx * ostr[d];
+        batch = q;
+    }
+    const long a0 = ta * 32, b0 = tb * 32, na = a.dd[ka], nb = a.dd[L];
+    // read: x along ka (source stride 1), y along the destination's last axis
+    for (int y = ty; y < 32; y += 8) {
+        const long ai = a0 + tx, bi = b0 + y;
+        if (ai < na && bi < nb) tile[y][tx] = src[in_base + ai + bi * a.ss[L]];
+    }
+    __syncthreads();
+    // write: x along the destination's last axis (stride 1), y along ka
+    for (int y = ty; y < 32; y += 8) {
+        const long ai = a0 + y, bi = b0 + tx;
+        if (ai < na && bi < nb) dst[out_base + ai * ostr[ka] + bi] = tile[tx][y];
+    }
+}
+
 // tiled 2-D transpose for the common case "swap two contiguous groups":
 // dst[b][c][r] = src[b][r][c]
 __global__ void transpose_kernel(const double *__restrict__ src, double *__restrict__ dst, long R, long Cc) {
@@ -305,6 +346,22 @@ void permute(const double *src, double *dst, const std::vector<int> &dims, const
     a.nd = nd;
     a.total = total;
     for (int i = 0; i < nd; ++i) { a.dd[i] = dims[perm[i]]; a.ss[i] = sstr[perm[i]]; }
+    // the source's unit-stride axis lands at dst axis ka; tile it against the
+    // dst's last axis when both are long enough to fill 32-wide rows
+    int ka = -1;
+    for (int i = 0; i < nd; ++i)
+        if (a.ss[i] == 1) ka = i;
+    if (ka >= 0 && ka != nd - 1 && a.dd[ka] >= 16 && a.dd[nd - 1] >= 16) {
+        const long nta = (a.dd[ka] + 31) / 32, ntb = (a.dd[nd - 1] + 31) / 32;
+        const long nbatch = total / (a.dd[ka] * a.dd[nd - 1]);
+        const long blocks = nta * ntb * nbatch;
+        if (blocks <= 2147483647L) {
+            hipLaunchKernelGGL(permute_tiled_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, a, ka, nta,
+                               ntb);
+            TRG_HIP_CHECK(hipGetLastError());
+            return;
+        }
+    }
     hipLaunchKernelGGL(permute_kernel, dim3(grid_for(total)), dim3(256), 0, st, src, dst, a);
     TRG_HIP_CHECK(hipGetLastError());
 }
