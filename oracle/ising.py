@@ -80,14 +80,37 @@ def enumerate_log_z_per_site(beta, h, extents):
     return _logsumexp(beta * e_bond + h * mag) / v
 
 
-def hte_4d(beta):
-    """High-temperature series of log Z/V (4D, h=0) through t^6, t = tanh beta.
+# Coefficients a_4, a_6, a_8 of the high-temperature series of log Z/V on the
+# d-dimensional hypercubic lattice (h = 0), in t = tanh(beta):
+#   log Z/V = ln 2 + d ln cosh(beta) + a_4 t^4 + a_6 t^6 + a_8 t^8 + O(t^10).
+# With Z = 2^V cosh^{dV}(beta) sum_G t^|G| over the even bond subgraphs G, the
+# cluster expansion of the logarithm gives a_4 = p_4, a_6 = p_6 (polygons per
+# site) and a_8 = p_8 + f_8 - c_8 / 2: f_8 pairs of plaquettes touching at one
+# site only (a connected even subgraph), c_8 ordered pairs of plaquettes that
+# share at least one site, a plaquette with itself included.  Per plaquette,
+# 2d - 3 others share each of its 4 edges and 8d^2 - 24d + 20 others share a
+# single site, so f_8 - c_8 / 2 = -(d(d-1)/4) (1 + 4(2d - 3)).  The polygon
+# counts p_n are 1, 2, 7 (2D), 3, 22, 207 (3D) and 6, 76, 1434 (4D).
+HTE_COEFFS = {2: (1.0, 2.0, 4.5), 3: (3.0, 22.0, 187.5), 4: (6.0, 76.0, 1371.0)}
 
-    log Z/V = ln 2 + 4 ln cosh b + 6 t^4 + 76 t^6 + O(t^8): 6 plaquettes per site
-    and 12 planar plus 64 non-planar 6-bond loops per site.
-    """
+
+def hte_series(beta, d=4, order=8):
+    """High-temperature series of log Z/V (h = 0, thermodynamic limit) through t^order."""
     t = math.tanh(beta)
-    return math.log(2.0) + 4.0 * math.log(math.cosh(beta)) + 6.0 * t ** 4 + 76.0 * t ** 6
+    a4, a6, a8 = HTE_COEFFS[d]
+    val = math.log(2.0) + d * math.log(math.cosh(beta))
+    for n, a in ((4, a4), (6, a6), (8, a8)):
+        if n <= order:
+            val += a * t ** n
+    return val
+
+
+def hte_4d(beta):
+    """High-temperature series of log Z/V (4D, h=0) through t^8, t = tanh beta.
+
+    log Z/V = ln 2 + 4 ln cosh b + 6 t^4 + 76 t^6 + 1371 t^8 + O(t^10).
+    """
+    return hte_series(beta, 4, 8)
 
 
 def lte_4d(beta):

@@ -1,11 +1,12 @@
 """Pins of the Ising initial tensor and of the exact results used as references."""
+import itertools
 import math
 
 import numpy as np
 import pytest
 
 from oracle.ising import (ising_w, ising_tensor, ising_cp, enumerate_log_z_per_site,
-                          onsager_log_z, onsager_log_z_1d, hte_4d, lte_4d)
+                          onsager_log_z, onsager_log_z_1d, hte_4d, lte_4d, hte_series, HTE_COEFFS)
 
 
 @pytest.mark.parametrize("beta", [0.0, 0.1497, 0.7])
@@ -92,3 +93,85 @@ def test_series_4d_leading_terms():
     # CP factors reproduce T
     phi, psi = ising_cp(0.3, 0.1, 4)
     assert np.allclose(np.tensordot(phi, psi, ([4], [4])), ising_tensor(0.3, 0.1, 4))
+
+
+# ---------------------------------------------------------------- series coefficients
+
+def _closed_walks(d, n):
+    """Rooted, directed closed self-avoiding walks of n steps on Z^d (brute force)."""
+    steps = []
+    for mu in range(d):
+        for s in (1, -1):
+            v = [0] * d
+            v[mu] = s
+            steps.append(tuple(v))
+    origin = (0,) * d
+    seen = {origin}
+    count = 0
+
+    def walk(pos, k):
+        nonlocal count
+        if k == n - 1:
+            if sum(abs(a) for a in pos) == 1:
+                count += 1
+            return
+        for st in steps:
+            nxt = tuple(a + b for a, b in zip(pos, st))
+            if nxt in seen or sum(abs(a) for a in nxt) > n - k - 1:
+                continue
+            seen.add(nxt)
+            walk(nxt, k + 1)
+            seen.discard(nxt)
+
+    walk(origin, 0)
+    return count
+
+
+def _plaquette_overlaps(d):
+    """For the plaquette at the origin in the (0, 1) plane: number of other plaquettes
+    sharing an edge with it and sharing exactly one site with it (brute force)."""
+    def sites(base, mu, nu):
+        e = [0] * d
+        f = [0] * d
+        e[mu] = 1
+        f[nu] = 1
+        b = tuple(base)
+        return {b, tuple(x + y for x, y in zip(b, e)), tuple(x + y for x, y in zip(b, f)),
+                tuple(x + y + z for x, y, z in zip(b, e, f))}
+
+    ref = sites((0,) * d, 0, 1)
+    edge = corner = 0
+    for base in itertools.product(range(-1, 2), repeat=d):
+        for mu in range(d):
+            for nu in range(mu + 1, d):
+                s = sites(base, mu, nu)
+                if s == ref:
+                    continue
+                k = len(s & ref)
+                if k == 2:
+                    edge += 1
+                elif k == 1:
+                    corner += 1
+    return edge, corner
+
+
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_series_coefficients_from_polygon_counts(d):
+    # a_4 = p_4, a_6 = p_6, a_8 = p_8 + f_8 - c_8 / 2 (cluster expansion of log of
+    # the even-subgraph sum); every count is done here by brute force
+    p = {n: _closed_walks(d, n) / (2 * n) for n in (4, 6, 8)}
+    nplaq = d * (d - 1) // 2
+    edge, corner = _plaquette_overlaps(d)
+    f8 = nplaq * corner / 2.0
+    c8 = nplaq * (1 + edge + corner)
+    a = (p[4], p[6], p[8] + f8 - c8 / 2.0)
+    assert a == HTE_COEFFS[d]
+
+
+@pytest.mark.parametrize("beta", [0.05, 0.08])
+def test_2d_series_against_onsager(beta):
+    # the same derivation in 2D against the exact solution: the residual after t^8
+    # is the t^10 term (12 t^10)
+    t = math.tanh(beta)
+    assert abs(onsager_log_z(beta) - hte_series(beta, 2, 8)) < 13 * t ** 10
+    assert abs(onsager_log_z(beta) - hte_series(beta, 2, 6)) > 4 * t ** 8

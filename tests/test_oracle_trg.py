@@ -94,6 +94,23 @@ def test_high_temperature_series():
     assert abs(lz - hte_4d(beta)) < 6 * math.tanh(beta) ** 4
 
 
+def test_high_temperature_deviation_shrinks_with_D():
+    # At beta = 0.05 the truncation error at D <= 8 is itself of order t^4 (the
+    # bond states that carry plaquettes across block faces outnumber D): the
+    # deviation from the series is 1.6e-5, 1.15e-5, 8.9e-6 at D = 4, 6, 8, above
+    # 76 t^6 = 1.2e-6, so the t^6 and t^8 terms are not resolved by the flow.
+    # What is checked: the flow lies below the series and approaches it as D grows.
+    beta = 0.05
+    t = math.tanh(beta)
+    dev = []
+    for D in (4, 6, 8):
+        lz, _ = trg.run(beta, 0.0, trg.Params(D=D, seed=1), 20, "triad")
+        dev.append(lz - hte_4d(beta))
+    assert all(v < 0 for v in dev)
+    assert abs(dev[0]) > abs(dev[1]) > abs(dev[2])
+    assert abs(dev[2]) < 1.5 * t ** 4
+
+
 def test_low_temperature_series():
     beta = 1.0
     lz, _ = trg.run(beta, 0.0, trg.Params(D=4), 40, "triad")
@@ -186,6 +203,40 @@ def test_bond_swap_sketch_is_exact_when_the_sketch_spans_the_range():
     p1 = x.reshape(-1, 1) @ np.diag(sig) @ y.reshape(-1, 1).T
     p2 = x2.reshape(-1, 1) @ np.diag(sig2) @ y2.reshape(-1, 1).T
     assert np.max(np.abs(p1 - p2)) < 1e-13 * sig[0]
+
+
+@pytest.mark.parametrize("power_iters", [0, 1, 2])
+def test_bond_swap_sketch_is_subspace_iteration(power_iters):
+    # rank(M) = 27 > m = 6: the randomized SVD is an approximation, and it must be
+    # the one of subspace iteration (Halko, Martinsson, Tropp, SIAM Rev. 2011):
+    # Q = orth((M M^T)^(q-1) M Omega) with q = power_iters + 1 passes, Omega the
+    # sketch drawn in M's column index (beta, j_perp), and the kept triplets those
+    # of the SVD of Q^T M, mapped back through Q.  Computed here on the explicit M.
+    from oracle.philox import sketch_omega
+    rng = np.random.default_rng(21)
+    xd, chi, tdim = 3, 3, (4, 4, 4)
+    bt = rng.standard_normal((xd,) + tdim + (chi,))
+    ct = rng.standard_normal((xd,) + tdim + (chi,))
+    m = _explicit_m(bt, ct)                          # (alpha, i_perp) x (beta, j_perp)
+    assert np.linalg.matrix_rank(m) == 27
+    D, step, seed = 3, 5, 99
+    prm = trg.Params(D=D, sketch_mult=2, power_iters=power_iters, seed=seed)
+    rec = {}
+    x, sig, y = trg.bond_swap(bt, ct, prm, step, rec)
+    assert rec["bond"]["mode"] == "sketch"
+    om = sketch_omega(seed, step, 0, chi, tdim, 2 * D).reshape(chi * 64, 2 * D)
+    yk = np.linalg.matrix_power(m @ m.T, power_iters) @ m @ om
+    q, _ = np.linalg.qr(yk)
+    u, sv, vt = np.linalg.svd(q.T @ m)
+    k = rec["bond"]["kept"]
+    assert k == D
+    assert np.allclose(sig[:k], sv[:k], rtol=1e-11, atol=0)
+    approx_ref = (q @ u[:, :k]) @ np.diag(sv[:k]) @ vt[:k]
+    xm = x.reshape(-1, x.shape[-1])[:, :k]
+    ym = y.reshape(-1, y.shape[-1])[:, :k]
+    assert np.max(np.abs(xm @ np.diag(sig[:k]) @ ym.T - approx_ref)) < 1e-11 * sv[0]
+    # the sketch is not the exact SVD here (so the check above is not vacuous)
+    assert np.max(np.abs(sig[:k] - np.linalg.svd(m, compute_uv=False)[:k])) > 1e-6 * sv[0]
 
 
 def _explicit_gamma(a, xs, y, dt):
