@@ -15,9 +15,15 @@
  *     memory escapes.  Host pointers passed in are only read (or written,
  *     for outputs) during the call.
  *   - Work is enqueued on the state's HIP stream (opt.stream, or the null
- *     stream when NULL).  Steps are asynchronous; log_z_per_site and the
- *     export/inspection calls synchronise the stream.  The caller keeps a
- *     stream it passed alive until trg_destroy.
+ *     stream when NULL).  A step reads the convergence flags of its
+ *     eigensolvers and SVDs and its numerical status back on the host, so it
+ *     returns with the stream synchronised; log_z_per_site and the
+ *     export/inspection calls synchronise it too.  The caller keeps a stream
+ *     it passed alive until trg_destroy.
+ *   - A step that fails leaves the state as it was before the step (tensors,
+ *     step count and log-norm accumulator), so log_z_per_site still gives
+ *     the value before the failed step.  If even that cannot be restored
+ *     (HIP error) the state asks for a new tensor_init (TRG_E_STATE).
  *   - Device: opt.device selects the GPU; the library makes it current for
  *     the duration of each call.
  */
@@ -148,6 +154,26 @@ const char *trg_batch_last_error(const trg_batch *b);
 
 /* Frees every instance and stream; NULL is a no-op. */
 int trg_batch_destroy(trg_batch *b);
+
+/* ---- device-memory building blocks ------------------------------------- */
+
+/*
+ * trg_qr -- thin QR factorisation A = Q R of a tall matrix in device memory,
+ * the factorisation of the re-split (Fig. 5f: QR of Phi and of Psi) and of
+ * the randomized SVD's sketches (App. A, the QR steps after eq. bond1 and
+ * eq. bond2), by the library's tall-skinny Householder QR.
+ *   A  device pointer, m x n row-major (read only), 1 <= n <= 64, m >= n;
+ *   Q  device pointer, m x n row-major (written), orthonormal columns;
+ *   R  device pointer, n x n row-major (written), upper triangular with a
+ *      non-negative diagonal.
+ * All three live on the calling thread's current HIP device and must not
+ * overlap.  stream: hipStream_t to enqueue on (NULL: the null stream).  The
+ * call allocates its scratch (about 3 m n doubles) with hipMalloc, runs,
+ * synchronises the stream and frees it.  TRG_E_INVALID for NULL pointers or
+ * bad sizes, TRG_E_NOMEM if the scratch cannot be allocated, TRG_E_HIP for a
+ * runtime error; trg_last_error(NULL) gives the message.
+ */
+int trg_qr(const double *A, int64_t m, int n, double *Q, double *R, void *stream);
 
 /* ---- inspection (tests and benchmarks) --------------------------------- */
 

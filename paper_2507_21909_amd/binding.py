@@ -90,6 +90,9 @@ def load_library(path=None):
     lib.trg_batch_last_error.argtypes = [ctypes.c_void_p]
     lib.trg_batch_last_error.restype = ctypes.c_char_p
     lib.trg_batch_destroy.argtypes = [ctypes.c_void_p]
+    lib.trg_qr.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_void_p]
+    lib.trg_qr.restype = ctypes.c_int
     for f in ("trg_batch_create", "trg_batch_run", "trg_batch_log_z", "trg_batch_size", "trg_batch_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     for f in ("trg_create", "trg_destroy", "tensor_init", "atrg_step", "triad_atrg_step", "log_z_per_site",
@@ -319,3 +322,27 @@ def selftest_sketch(seed, step, instance, chi, jdims, m):
     out = np.empty((chi, jd[0], jd[1], jd[2], m))
     _check(lib.trg_selftest_sketch(seed, step, instance, chi, jd[0], jd[1], jd[2], m, _p(out)))
     return out.reshape([chi] + list(jdims) + [m])
+
+
+def _device_args(a, n_max=64):
+    """Checks a torch float64 CUDA matrix and returns (m, n, stream handle)."""
+    import torch
+    if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64 and a.dim() == 2
+            and a.is_contiguous()):
+        raise ValueError("a contiguous float64 CUDA matrix is required")
+    m, n = a.shape
+    if not (1 <= n <= n_max and m >= n):
+        raise ValueError("needs 1 <= n <= %d and m >= n (got %d x %d)" % (n_max, m, n))
+    return m, n, torch.cuda.current_stream(a.device).cuda_stream
+
+
+def qr(a):
+    """Thin QR of a float64 CUDA matrix (trg_qr) on torch's current stream: (Q, R) CUDA tensors."""
+    import torch
+    lib = load_library()
+    m, n, st = _device_args(a)
+    q = torch.empty((m, n), dtype=torch.float64, device=a.device)
+    r = torch.empty((n, n), dtype=torch.float64, device=a.device)
+    with torch.cuda.device(a.device):
+        _check(lib.trg_qr(a.data_ptr(), m, n, q.data_ptr(), r.data_ptr(), st))
+    return q, r

@@ -26,8 +26,8 @@ struct trg_state {
     std::vector<int> dims;
     double *phi = nullptr, *psi = nullptr;   // persistent state
     size_t cap_state = 0;
-    double *dscal = nullptr;   // [0] logacc, [1] trace, [2..] scratch
-    int *dint = nullptr;       // [0] numerical status, [8..] kept counts
+    double *dscal = nullptr;   // [0] logacc, [1] trace, [3] logacc before the step, [1024..2048) trace partials
+    int *dint = nullptr;       // [0] numerical status, [1] status before the step, [8..] kept counts
     std::vector<double> sigma_last;
     std::string err;
     bool timing = false;
@@ -828,6 +828,9 @@ void do_step(trg_state *S, int axis, bool triad) {
     TRG_REQUIRE(d == 4, -6, "the GPU path implements d = 4");
     S->ar.reset();
     Step T(S);
+    // accumulator and status before the step (dscal[3], dint[1]); restored if the step fails
+    copy(S->dscal + 3, S->dscal, 1, S->st);
+    TRG_HIP_CHECK(hipMemcpyAsync(S->dint + 1, S->dint, sizeof(int), hipMemcpyDeviceToDevice, S->st));
     std::vector<int> order(d);
     for (int i = 0; i < d; ++i) order[i] = (axis + i) % d;
     Split sp = resplit(T, order);
@@ -842,6 +845,16 @@ void do_step(trg_state *S, int axis, bool triad) {
     stp += 'z';
     nat += 'z';
     TRG_REQUIRE((size_t)phi.n() <= S->cap_state && (size_t)psi.n() <= S->cap_state, -6, "state exceeds D^5");
+    // numerical status of the step (norm, multiplet sizes) before the state is overwritten
+    std::vector<double> sig(sw.sig.d[0], 0.0);
+    int status = 0;
+    TRG_HIP_CHECK(hipMemcpyAsync(sig.data(), sw.sig.p, sizeof(double) * sig.size(), hipMemcpyDeviceToHost, S->st));
+    TRG_HIP_CHECK(hipMemcpyAsync(&status, S->dint, sizeof(int), hipMemcpyDeviceToHost, S->st));
+    TRG_HIP_CHECK(hipStreamSynchronize(S->st));
+    TRG_REQUIRE(status != 1, -4, "non-positive or non-finite norm at the re-split");
+    TRG_REQUIRE(status != 2, -4, "a truncation cut falls in a multiplet of more than 16 values (canonical basis "
+                                 "not formed); raise tau_deg's resolution or change D");
+    TRG_REQUIRE(status == 0, -4, "numerical status flag set");
     std::vector<int> perm(d + 1);
     for (int i = 0; i <= d; ++i) perm[i] = (int)stp.find(nat[i]);
     permute(phi.p, S->phi, phi.d, perm, S->st);
@@ -850,8 +863,7 @@ void do_step(trg_state *S, int axis, bool triad) {
     for (int i = 0; i < d; ++i) nd[i] = phi.d[perm[i]];
     S->dims = nd;
     S->chi = phi.d[d];
-    S->sigma_last.assign(sw.sig.d[0], 0.0);
-    TRG_HIP_CHECK(hipMemcpyAsync(S->sigma_last.data(), sw.sig.p, sizeof(double) * sw.sig.d[0], hipMemcpyDeviceToHost, S->st));
+    S->sigma_last = sig;
     TRG_HIP_CHECK(hipStreamSynchronize(S->st));
     for (auto &t : T.c.timed) {
         float ms = 0.0f;
@@ -925,7 +937,7 @@ int trg_create(const trg_options *opt, trg_state **out) {
         DevGuard g(opt->device);
         s->st = static_cast<hipStream_t>(opt->stream);
         s->ar.set_cap(opt->workspace_cap);
-        TRG_HIP_CHECK(hipMalloc(&s->dscal, 64 * sizeof(double)));
+        TRG_HIP_CHECK(hipMalloc(&s->dscal, 2048 * sizeof(double)));
         TRG_HIP_CHECK(hipMalloc(&s->dint, 256 * sizeof(int)));
     } catch (const Error &e) {
         g_err = e.what();
@@ -958,12 +970,23 @@ int tensor_init(trg_state *s, int model, double beta, double h, int D) {
         const int d = s->opt.dim;
         size_t cap = 1;
         for (int i = 0; i <= d; ++i) cap *= (size_t)std::max(D, 2);
+        s->init = false;   // set again only once the new state is complete
         if (cap > s->cap_state) {
+            if (s->st) (void)hipStreamSynchronize(s->st);
             if (s->phi) (void)hipFree(s->phi);
             if (s->psi) (void)hipFree(s->psi);
             s->phi = s->psi = nullptr;
-            TRG_HIP_CHECK(hipMalloc(&s->phi, cap * sizeof(double)));
-            TRG_HIP_CHECK(hipMalloc(&s->psi, cap * sizeof(double)));
+            s->cap_state = 0;
+            s->dims.clear();
+            s->chi = 0;
+            if (hipMalloc(&s->phi, cap * sizeof(double)) != hipSuccess ||
+                hipMalloc(&s->psi, cap * sizeof(double)) != hipSuccess) {
+                (void)hipGetLastError();
+                if (s->phi) (void)hipFree(s->phi);
+                if (s->psi) (void)hipFree(s->psi);
+                s->phi = s->psi = nullptr;
+                throw Error(TRG_E_NOMEM, "tensor_init: cannot allocate the D^5 state tensors");
+            }
             s->cap_state = cap;
         }
         // CP form: Phi[i_1..i_d, a] = e^{h s_a} prod W[a, i_mu], Psi = prod W[a, j_mu]
@@ -1004,6 +1027,24 @@ int tensor_init(trg_state *s, int model, double beta, double h, int D) {
     return TRG_OK;
 }
 
+// A failed step leaves phi, psi and k as they were; the log-norm accumulator and
+// the status flag are put back to their values before the step (a step adds its
+// 2^-k log c_k at the re-split, before any later part can fail).
+static void rollback(trg_state *s) {
+    if (hipSetDevice(s->opt.device) != hipSuccess) return;
+    (void)hipStreamSynchronize(s->st);
+    (void)hipGetLastError();
+    bool ok = hipMemcpyAsync(s->dscal, s->dscal + 3, sizeof(double), hipMemcpyDeviceToDevice, s->st) == hipSuccess &&
+              hipMemcpyAsync(s->dint, s->dint + 1, sizeof(int), hipMemcpyDeviceToDevice, s->st) == hipSuccess &&
+              hipStreamSynchronize(s->st) == hipSuccess;
+    if (!ok) {
+        // the accumulator could not be restored: the state needs a new tensor_init
+        (void)hipGetLastError();
+        s->init = false;
+        s->err += " (state invalidated; call tensor_init)";
+    }
+}
+
 static int step_common(trg_state *s, int axis, bool triad) {
     if (!s) return TRG_E_INVALID;
     if (!s->init) {
@@ -1018,15 +1059,17 @@ static int step_common(trg_state *s, int axis, bool triad) {
         s->err = "triad-ATRG needs dim 4";
         return TRG_E_INVALID;
     }
+    int rc = TRG_OK;
     try {
         DevGuard g(s->opt.device);
         trg::do_step(s, axis, triad);
     } catch (const Error &e) {
-        return fail(s, e);
+        rc = fail(s, e);
     } catch (const std::exception &e) {
-        return fail_std(s, e);
+        rc = fail_std(s, e);
     }
-    return TRG_OK;
+    if (rc != TRG_OK) rollback(s);
+    return rc;
 }
 
 int atrg_step(trg_state *s, int axis) { return step_common(s, axis, false); }
@@ -1039,7 +1082,7 @@ int log_z_per_site(trg_state *s, double *out) {
         DevGuard g(s->opt.device);
         long n = (long)s->chi;
         for (int v : s->dims) n *= v;
-        double *part = static_cast<double *>(s->ar.alloc(1024 * sizeof(double)));
+        double *part = s->dscal + 1024;
         hipLaunchKernelGGL(trg::dot_partial_kernel, dim3(1024), dim3(256), 0, s->st, s->phi, s->psi, n, part);
         hipLaunchKernelGGL(trg::sum_kernel, dim3(1), dim3(256), 0, s->st, part, 1024, s->dscal + 1);
         double hs[2];
@@ -1047,7 +1090,8 @@ int log_z_per_site(trg_state *s, double *out) {
         TRG_HIP_CHECK(hipMemcpyAsync(hs, s->dscal, sizeof(hs), hipMemcpyDeviceToHost, s->st));
         TRG_HIP_CHECK(hipMemcpyAsync(&status, s->dint, sizeof(int), hipMemcpyDeviceToHost, s->st));
         TRG_HIP_CHECK(hipStreamSynchronize(s->st));
-        if (status != 0) throw Error(TRG_E_NUMERICAL, "non-positive or non-finite norm at a re-split");
+        if (status == 1) throw Error(TRG_E_NUMERICAL, "non-positive or non-finite norm at a re-split");
+        if (status != 0) throw Error(TRG_E_NUMERICAL, "numerical status flag set by an earlier step");
         if (!(hs[1] > 0.0) || !std::isfinite(hs[1])) throw Error(TRG_E_NUMERICAL, "final trace is not positive");
         *out = hs[0] + std::ldexp(std::log(hs[1]), -s->k);
     } catch (const Error &e) {
@@ -1127,6 +1171,31 @@ const char *trg_strerror(int code) {
 }
 
 const char *trg_last_error(trg_state *s) { return s ? s->err.c_str() : g_err.c_str(); }
+
+int trg_qr(const double *A, int64_t m, int n, double *Q, double *R, void *stream) {
+    if (!A || !Q || !R || n < 1 || n > 64 || m < n) {
+        g_err = "trg_qr: needs non-NULL A, Q, R, 1 <= n <= 64 and m >= n";
+        return TRG_E_INVALID;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *ws = nullptr;
+    if (hipMalloc(&ws, trg::tsqr_ws_doubles(m, n) * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        g_err = "trg_qr: cannot allocate the QR scratch";
+        return TRG_E_NOMEM;
+    }
+    int rc = TRG_OK;
+    try {
+        trg::tsqr(A, m, n, Q, R, ws, st);
+        TRG_HIP_CHECK(hipStreamSynchronize(st));
+    } catch (const Error &e) {
+        g_err = e.what();
+        rc = e.code;
+        (void)hipStreamSynchronize(st);
+    }
+    (void)hipFree(ws);
+    return rc;
+}
 
 }  // extern "C"
 
