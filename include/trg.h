@@ -175,6 +175,25 @@ int trg_batch_destroy(trg_batch *b);
  */
 int trg_qr(const double *A, int64_t m, int n, double *Q, double *R, void *stream);
 
+/*
+ * trg_qr_noalloc -- trg_qr for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as trg_qr, bit for bit,
+ * but the call allocates nothing: its scratch is a fixed 64 MiB device array
+ * inside the library (one per GPU, held until the process ends), and it does
+ * not synchronise: the QR is enqueued on `stream` and the call returns.
+ *   Limit: the QR's scratch (about 3 m n doubles: 256-row blocks of every
+ *   TSQR level plus two Q-rebuild buffers) must fit 8 Mi doubles; every
+ *   m * n <= 2097152 does (e.g. m <= 35584 at n = 64).  Larger sizes return
+ *   TRG_E_UNSUPPORTED before anything is enqueued; use trg_qr for them.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one
+ * device (two streams, or two host threads) race and give wrong results;
+ * serialise them on one stream.  The scratch keeps the last call's contents,
+ * which no call reads.  TRG_E_INVALID for NULL pointers or bad sizes,
+ * TRG_E_HIP for a runtime error; trg_last_error(NULL) gives the message.
+ */
+int trg_qr_noalloc(const double *A, int64_t m, int n, double *Q, double *R, void *stream);
+
 /* ---- inspection (tests and benchmarks) --------------------------------- */
 
 /* Names accepted by trg_export (host copy of a device tensor). */

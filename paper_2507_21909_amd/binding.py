@@ -93,6 +93,8 @@ def load_library(path=None):
     lib.trg_qr.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                            ctypes.c_void_p]
     lib.trg_qr.restype = ctypes.c_int
+    lib.trg_qr_noalloc.argtypes = lib.trg_qr.argtypes
+    lib.trg_qr_noalloc.restype = ctypes.c_int
     for f in ("trg_batch_create", "trg_batch_run", "trg_batch_log_z", "trg_batch_size", "trg_batch_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     for f in ("trg_create", "trg_destroy", "tensor_init", "atrg_step", "triad_atrg_step", "log_z_per_site",
@@ -345,4 +347,22 @@ def qr(a):
     r = torch.empty((n, n), dtype=torch.float64, device=a.device)
     with torch.cuda.device(a.device):
         _check(lib.trg_qr(a.data_ptr(), m, n, q.data_ptr(), r.data_ptr(), st))
+    return q, r
+
+
+def qr_noalloc(a, q=None, r=None):
+    """trg_qr_noalloc: thin QR of a float64 CUDA matrix into caller-provided (or new) Q and R, enqueued
+    on torch's current stream without any device allocation by the library (no synchronisation)."""
+    import torch
+    lib = load_library()
+    m, n, st = _device_args(a)
+    if q is None:
+        q = torch.empty((m, n), dtype=torch.float64, device=a.device)
+    if r is None:
+        r = torch.empty((n, n), dtype=torch.float64, device=a.device)
+    for t, shp in ((q, (m, n)), (r, (n, n))):
+        if not (t.is_cuda and t.dtype == torch.float64 and tuple(t.shape) == shp and t.is_contiguous()):
+            raise ValueError("Q and R must be contiguous float64 CUDA tensors of shapes %s and %s" % ((m, n), (n, n)))
+    with torch.cuda.device(a.device):
+        _check(lib.trg_qr_noalloc(a.data_ptr(), m, n, q.data_ptr(), r.data_ptr(), st))
     return q, r

@@ -13,6 +13,8 @@
 // get the sign convention of the weight w(multi-index).
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 #include "engine.h"
 
@@ -1195,6 +1197,74 @@ int trg_qr(const double *A, int64_t m, int n, double *Q, double *R, void *stream
     }
     (void)hipFree(ws);
     return rc;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- allocation-free thin QR
+namespace {
+// Scratch of trg_qr_noalloc: 8 Mi doubles (64 MiB) in the code object's device
+// globals, one copy per GPU the library runs on, held until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is only
+// a stand-in symbol); it uses the device address that hipGetSymbolAddress
+// returns, fetched once per device and kept in qr_scratch_dev.
+constexpr size_t kQrScratchDoubles = size_t(8) << 20;
+static __device__ __align__(256) double qr_scratch[kQrScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_qr_scratch_mu;
+double *qr_scratch_dev[kMaxDevices] = {};
+
+// Device address of qr_scratch on the current device (looked up on the first
+// call on that device); nullptr with g_err set on failure.
+double *qr_scratch_ptr() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        g_err = "trg_qr_noalloc: no usable current HIP device";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_qr_scratch_mu);
+    if (!qr_scratch_dev[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(qr_scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            g_err = std::string("trg_qr_noalloc: hipGetSymbolAddress of the scratch failed: ") +
+                    hipGetErrorString(e);
+            return nullptr;
+        }
+        qr_scratch_dev[dev] = static_cast<double *>(p);
+    }
+    return qr_scratch_dev[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int trg_qr_noalloc(const double *A, int64_t m, int n, double *Q, double *R, void *stream) {
+    if (!A || !Q || !R || n < 1 || n > 64 || m < n) {
+        g_err = "trg_qr_noalloc: needs non-NULL A, Q, R, 1 <= n <= 64 and m >= n";
+        return TRG_E_INVALID;
+    }
+    const size_t need = trg::tsqr_ws_doubles(m, n);
+    if (need > kQrScratchDoubles) {
+        g_err = "trg_qr_noalloc: an m x n QR needs " + std::to_string(need) +
+                " doubles of scratch, above the fixed " + std::to_string(kQrScratchDoubles) +
+                " (every m * n <= 2097152 fits); use trg_qr";
+        return TRG_E_UNSUPPORTED;
+    }
+    double *ws = qr_scratch_ptr();
+    if (!ws) return TRG_E_HIP;
+    try {
+        // every scratch element the kernels read is written earlier in the
+        // same call, so the previous call's contents need no clearing
+        trg::tsqr(A, m, n, Q, R, ws, static_cast<hipStream_t>(stream));
+    } catch (const Error &e) {
+        g_err = e.what();
+        return e.code;
+    }
+    return TRG_OK;
 }
 
 }  // extern "C"

@@ -212,7 +212,8 @@ void tsqr(const double *a, long m, int n, double *q, double *r, double *ws, hipS
     }();
     if (trace) fprintf(stderr, "[tsqr] m %ld n %d\n", m, n);
     const int BR = RB;
-    std::vector<Level> lv;
+    Level lv[64];   // rows shrink by 4x or more per level: far fewer levels than this
+    int nlv = 0;
     double *p = ws;
     const double *in = a;
     long rows = m;
@@ -230,7 +231,8 @@ void tsqr(const double *a, long m, int n, double *q, double *r, double *ws, hipS
         else if (n <= 32) launch_block_reg<32>(L.nb, in, rows, n, rs, L.q, fin, st);
         else launch_block_reg<64>(L.nb, in, rows, n, rs, L.q, fin, st);
         TRG_HIP_CHECK(hipGetLastError());
-        lv.push_back(L);
+        TRG_REQUIRE(nlv < 64, -6, "tsqr: too many levels");
+        lv[nlv++] = L;
         if (fin) {
             copy(r, rs, (size_t)n * n, st);
             break;
@@ -241,8 +243,8 @@ void tsqr(const double *a, long m, int n, double *q, double *r, double *ws, hipS
     // rebuild Q top-down
     long nb0 = lv[0].nb;
     double *bufA = p, *bufB = p + (size_t)nb0 * BR * n;
-    const double *upper = lv.back().q;   // rows_L x n (padded to BR)
-    for (int l = (int)lv.size() - 2; l >= 0; --l) {
+    const double *upper = lv[nlv - 1].q;   // rows_L x n (padded to BR)
+    for (int l = nlv - 2; l >= 0; --l) {
         double *dst = (l % 2 == 0) ? bufA : bufB;
         GemmArgs g{};
         g.M = BR; g.N = n; g.K = n; g.batch = lv[l].nb;
