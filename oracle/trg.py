@@ -46,7 +46,8 @@ from .ising import ising_cp
 class Params:
     D: int
     r: int = 7
-    sketch_mult: int = 2
+    sketch_mult: int = 2          # sketch width m = sketch_mult * D (App. A footnote: eta = r_bond + 1)
+    r_bond: int = 1               # bond-swap overspanning (Sec. II C): keep r_bond * D bond values
     power_iters: int = 1
     seed: int = 0
     instance: int = 0
@@ -131,7 +132,9 @@ def bond_swap(bt, ct, prm, step, logrec):
     power_iters + 1 passes.  The Gaussian sketch is drawn in the (beta, j_perp)
     index space of M and projected on the QR basis of B.
     Returns X[alpha, i_t.., g], sigma[g], Y[beta, j_t.., g] with g padded to
-    min(D, rows(N), cols(N)).
+    min(r_bond D, rows(N), cols(N)): with r_bond > 1 the bond is overspanned
+    (ILO triad-ATRG, Sec. II C), and the next step's alpha and beta carry
+    r_bond D values through the re-split.
     """
     xdim = bt.shape[0]
     chia = bt.shape[-1]
@@ -150,7 +153,7 @@ def bond_swap(bt, ct, prm, step, logrec):
     rc3 = rc.reshape(q, xdim, chib)
     n = np.einsum("pxa,qxb->aqbp", rb3, rc3).reshape(chia * q, chib * p)
     rows, cols = n.shape
-    gcap = min(prm.D, rows, cols)
+    gcap = min(prm.r_bond * prm.D, rows, cols)
     m = prm.sketch_mult * prm.D
     if prm.bond_svd == "exact" or m >= min(rows, cols):
         ub, sig, vb = jacobi_svd(n)
@@ -460,6 +463,30 @@ def log_z_per_site(state):
     if not (tr > 0 and np.isfinite(tr)):
         raise FloatingPointError("final trace %r is not positive" % tr)
     return state.logacc + 2.0 ** (-state.k) * math.log(tr)
+
+
+def gu_wen_matrix(state, axis):
+    """A[k, l] = sum of T over every leg pair but ``axis`` traced (forward leg =
+    backward leg), with k the forward and l the backward leg along ``axis``
+    (Sec. III D, the matrix of the dimensionless ratio X).  With
+    T = sum_g Phi[.., g] Psi[.., g]: A = sum_{I, g} Phi[I_k, g] Psi[I_l, g]."""
+    n = state.phi.shape[axis]
+    phi = np.moveaxis(state.phi, axis, 0).reshape(n, -1)
+    psi = np.moveaxis(state.psi, axis, 0).reshape(n, -1)
+    return phi @ psi.T
+
+
+def gu_wen_x(state, axis=None):
+    """X = (Tr A)^2 / Tr(A A) of the current coarse tensor (Sec. III D); the
+    paper's A keeps the fourth leg open, which is the default axis d - 1.
+    X is 1 for a tensor of rank one along ``axis`` (disordered phase) and 2 for
+    two degenerate ground states (ordered phase)."""
+    if axis is None:
+        axis = state.d - 1
+    if not 0 <= axis < state.d:
+        raise ValueError("axis out of range")
+    a = gu_wen_matrix(state, axis)
+    return float(np.trace(a) ** 2 / np.trace(a @ a))
 
 
 def run(beta, h, prm, nsteps, method="triad", d=4, start_axis=0):
