@@ -151,22 +151,32 @@ def bond_swap(bt, ct, prm, step, logrec):
     q = rc.shape[0]
     rb3 = rb.reshape(p, xdim, chia)
     rc3 = rc.reshape(q, xdim, chib)
-    n = np.einsum("pxa,qxb->aqbp", rb3, rc3).reshape(chia * q, chib * p)
-    rows, cols = n.shape
+    rows, cols = chia * q, chib * p
     gcap = min(prm.r_bond * prm.D, rows, cols)
     m = prm.sketch_mult * prm.D
     if prm.bond_svd == "exact" or m >= min(rows, cols):
+        n = np.einsum("pxa,qxb->aqbp", rb3, rc3).reshape(rows, cols)
         ub, sig, vb = jacobi_svd(n)
         mode = "exact"
     else:
+        # the core is never formed: eq. bond1 applies R^B to the sketch, then
+        # R^C; eq. bond2 applies R^C to Q, then R^B
+        def apply_n(om):
+            t = np.einsum("pxa,bpm->xabm", rb3, om.reshape(chib, p, -1), optimize=True)
+            return np.einsum("qxb,xabm->aqm", rc3, t, optimize=True).reshape(rows, -1)
+
+        def apply_nt(qm):
+            t = np.einsum("qxb,aqm->xabm", rc3, qm.reshape(chia, q, -1), optimize=True)
+            return np.einsum("pxa,xabm->bpm", rb3, t, optimize=True).reshape(cols, -1)
+
         om_full = sketch_omega(prm.seed, step, prm.instance, chib, jdims, m)
         om = np.einsum("jp,bjm->bpm", qb, om_full.reshape(chib, jn, m)).reshape(chib * p, m)
         qy = None
         rp = None
         for _ in range(prm.power_iters + 1):
-            y = n @ om
+            y = apply_n(om)
             qy, _r = qr_pos(y)
-            yt = n.T @ qy
+            yt = apply_nt(qy)
             qp, rp = qr_pos(yt)
             om = qp
         ut, sig, w = jacobi_svd(rp.T)

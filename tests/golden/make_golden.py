@@ -9,7 +9,8 @@ with, after every step, log Z/V and the gauge-invariant spectra of the step:
 * ``sq_s``       for each transverse position, the squeezer singular values
                  (relative to the largest, first D + 1) and ``sq_kept``
                  (null for an identity squeezer);
-* ``triad_kept`` kept columns of the four triad isometries (null: identity).
+* ``triad_kept`` kept columns of the four triad isometries (null: identity);
+* ``gu_wen_x``   the Gu-Wen ratio X with the open leg along each axis.
 
 A GPU run of the same flow is compared with these step by step.
 """
@@ -48,6 +49,15 @@ for _i, (_b, _h) in enumerate(_GRID):
     CASES[_name + "_t7"] = dict(beta=_b, h=_h, D=16, nsteps=80, seed=BASE + 3000 + _i, method="triad",
                                 tau_deg=1e-7)
 
+# ILO triad-ATRG (Sec. II C): the bond swap keeps r_bond D values, sketch
+# width (r_bond + 1) D; the paper's own runs use r_bond = 5
+CASES["ilo_d16_rb2_16steps"] = dict(beta=0.1497, h=0.0, D=16, nsteps=16, seed=BASE + 4000, method="triad",
+                                    r_bond=2, sketch_mult=3)
+CASES["ilo_d12_rb6_8steps"] = dict(beta=0.1497, h=1e-4, D=12, nsteps=8, seed=BASE + 4001, method="triad",
+                                   r_bond=6, sketch_mult=7)
+CASES["ilo_d16_rb5_6steps"] = dict(beta=0.1497, h=0.0, D=16, nsteps=6, seed=BASE + 4002, method="triad",
+                                   r_bond=5, sketch_mult=6)
+
 # Multiplet-tolerance study: the D 16 flow of triad_d16_l1024 at other tolerances
 # (0: only exact ties are kept together, i.e. the plain cap at D).
 for _t in (0.0, 1e-12, 1e-7):
@@ -82,15 +92,17 @@ def _spectra(rec, D):
 
 def main(name):
     c = CASES[name]
-    prm = trg.Params(D=c["D"], seed=c["seed"], tau_deg=c.get("tau_deg", 1e-9))
+    prm = trg.Params(D=c["D"], seed=c["seed"], tau_deg=c.get("tau_deg", 1e-9), r_bond=c.get("r_bond", 1),
+                     sketch_mult=c.get("sketch_mult", 2))
     st = trg.init_ising(c["beta"], c["h"], 4)
-    out = dict(case=name, params=c, log_z=[], seconds=[], spectra=[])
+    out = dict(case=name, params=c, log_z=[], seconds=[], spectra=[], gu_wen_x=[])
     for i in range(c["nsteps"]):
         t0 = time.time()
         trg.rg_step(st, i % 4, prm, c["method"])
         out["log_z"].append(trg.log_z_per_site(st))
         out["seconds"].append(time.time() - t0)
         out["spectra"].append(_spectra(st.log[-1], c["D"]))
+        out["gu_wen_x"].append([trg.gu_wen_x(st, ax) for ax in range(4)])
         gaps = [v.get("gap") for v in st.log[-1].values() if isinstance(v, dict) and v.get("gap") is not None]
         print("%s step %d log_z %.16f  %.1fs  min gap %s" % (name, i, out["log_z"][-1], out["seconds"][-1],
                                                             min(gaps) if gaps else None), flush=True)
