@@ -80,6 +80,45 @@ def enumerate_log_z_per_site(beta, h, extents):
     return _logsumexp(beta * e_bond + h * mag) / v
 
 
+def enumerate_derivatives_per_site(beta, h, extents):
+    """(d/dbeta, d/dh) of log Z / V on the same torus by enumeration:
+    <sum_{n,mu} s_n s_{n+mu}> / V and <sum_n s_n> / V (Boltzmann averages)."""
+    extents = tuple(int(e) for e in extents)
+    v = int(np.prod(extents))
+    if v > 22:
+        raise ValueError("enumeration limited to V <= 22")
+    sites = list(itertools.product(*[range(e) for e in extents]))
+    index = {s: i for i, s in enumerate(sites)}
+    bonds = []
+    for s in sites:
+        for mu, e in enumerate(extents):
+            t = list(s)
+            t[mu] = (t[mu] + 1) % e
+            bonds.append((index[s], index[tuple(t)]))
+    bonds = np.array(bonds, dtype=np.int64)
+    n = np.arange(2 ** v, dtype=np.int64)
+    spins = 1 - 2 * ((n[:, None] >> np.arange(v)[None, :]) & 1)
+    e_bond = np.sum(spins[:, bonds[:, 0]] * spins[:, bonds[:, 1]], axis=1).astype(np.float64)
+    mag = np.sum(spins, axis=1).astype(np.float64)
+    x = beta * e_bond + h * mag
+    w = np.exp(x - np.max(x))
+    z = np.sum(w)
+    return float(np.sum(w * e_bond) / z / v), float(np.sum(w * mag) / z / v)
+
+
+def onsager_energy(beta):
+    """Onsager's internal energy per site of the 2D model (H = -sum s s):
+    u = -coth(2b) [1 + (2/pi)(2 tanh^2(2b) - 1) K(k)], k = 2 sinh 2b / cosh^2 2b,
+    with K the complete elliptic integral of the first kind (here by the
+    arithmetic-geometric mean: K(k) = pi / (2 AGM(1, sqrt(1 - k^2))))."""
+    k = 2 * math.sinh(2 * beta) / math.cosh(2 * beta) ** 2
+    a, b = 1.0, math.sqrt(max(0.0, 1.0 - k * k))
+    for _ in range(60):
+        a, b = 0.5 * (a + b), math.sqrt(a * b)
+    kk = math.pi / (2 * a)
+    return -(1.0 / math.tanh(2 * beta)) * (1 + (2 / math.pi) * (2 * math.tanh(2 * beta) ** 2 - 1) * kk)
+
+
 # Coefficients a_4, a_6, a_8 of the high-temperature series of log Z/V on the
 # d-dimensional hypercubic lattice (h = 0), in t = tanh(beta):
 #   log Z/V = ln 2 + d ln cosh(beta) + a_4 t^4 + a_6 t^6 + a_8 t^8 + O(t^10).

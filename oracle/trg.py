@@ -82,7 +82,7 @@ def init_ising(beta, h, d=4):
 # step pieces
 # ----------------------------------------------------------------------------
 
-def resplit(phi, psi, eps_s, tau_deg=1e-9):
+def resplit(phi, psi, eps_s, tau_deg=1e-9, keep=None):
     """Exact SVD of T = Phi Psi^T through two QRs and a small SVD.
 
     Returns (A, B, C, Dm, c, s) as matrices with rows = legs in natural order:
@@ -90,7 +90,8 @@ def resplit(phi, psi, eps_s, tau_deg=1e-9):
     bond basis is canonical: within each multiplet of singular values the
     columns of A (and Dm) are rotated by the canonical rotation R, and
     B = Dm S', C = A S' with S' = R^T diag(s) R.  Columns whose singular value
-    is <= eps_s are zero in all four.
+    is <= eps_s are zero in all four.  ``keep`` (a dict), if given, receives
+    the canonical rotation R.
     """
     dims = phi.shape[:-1]
     f = int(np.prod(dims))
@@ -112,6 +113,8 @@ def resplit(phi, psi, eps_s, tau_deg=1e-9):
     a[:, k:] = 0.0
     dm[:, k:] = 0.0
     sp = rot.T @ np.diag(s) @ rot
+    if keep is not None:
+        keep["rot"] = rot
     return a, dm @ sp, a @ sp, dm, c, s
 
 
@@ -289,7 +292,7 @@ def squeezer(kf, kb, dt, db, prm, name, logrec):
     return eo.reshape(dt, db, prm.D), fo.reshape(dt, db, prm.D)
 
 
-def atrg_coarse(a, x, sig, y, dt, prm, logrec):
+def atrg_coarse(a, x, sig, y, dt, prm, logrec, keep=None):
     """ATRG coarse-graining (makeG / makeH) with squeezers from canonical Gamma^ATRG.
 
     a[i_a, t.., alpha], x[alpha, b.., g], y[beta, t.., g], dt[j_a, b.., beta].
@@ -323,6 +326,8 @@ def atrg_coarse(a, x, sig, y, dt, prm, logrec):
     ja, be = 3, 4
     hnew = _chain([(dt, [ja] + bl + [be]), (fs[0], [tl[0], bl[0], kl[0]]), (y, [be] + tl + [g])]
                   + [(fs[p], [tl[p], bl[p], kl[p]]) for p in range(1, d - 1)], [ja] + kl + [g])
+    if keep is not None:
+        keep.update(es=es, fs=fs)
     return gnew, hnew
 
 
@@ -384,7 +389,7 @@ def make_psi(g, h, tk, tl, n1, n2, n3):
     return np.einsum("xYDcg,YDkl->xklcg", ghn, klnn, optimize=True)
 
 
-def triad_coarse(a, x, sig, y, dt, prm, logrec):
+def triad_coarse(a, x, sig, y, dt, prm, logrec, keep=None):
     """Triad-ATRG coarse-graining (Sec. II B), d = 4.
 
     a[i_a, t1, t2, t3, alpha], x[alpha, t1, t2, t3, g], y[beta, t1, t2, t3, g],
@@ -428,11 +433,16 @@ def triad_coarse(a, x, sig, y, dt, prm, logrec):
     (m1, n1), (m2, n2), (m3, n3) = sq
     phi = make_phi(e, f, ti, tj, m1, m2, m3)
     psi = make_psi(g, h, tk, tl, n1, n2, n3)
+    if keep is not None:
+        keep.update(e=e, f=f, g=g, h=h, ti=ti, tj=tj, tk=tk, tl=tl, m=(m1, m2, m3), n=(n1, n2, n3))
     return phi, psi
 
 
-def rg_step(state, axis, prm, method):
-    """One coarse-graining step along ``axis`` ("atrg" or "triad")."""
+def rg_step(state, axis, prm, method, keep=None):
+    """One coarse-graining step along ``axis`` ("atrg" or "triad").
+
+    ``keep`` (a dict), if given, receives the step's inputs, its re-split, bond
+    swap, isometries and squeezers (the impurity method reuses them)."""
     d = state.d
     if not 0 <= axis < d:
         raise ValueError("axis out of range")
@@ -440,7 +450,9 @@ def rg_step(state, axis, prm, method):
         raise ValueError("triad-ATRG is defined for d = 4")
     order = [axis] + [(axis + i) % d for i in range(1, d)]
     rec = dict(step=state.k, axis=axis, method=method)
-    am, bm, cm, dm, c, s = resplit(state.phi, state.psi, prm.eps_s, prm.tau_deg)
+    if keep is not None:
+        keep.update(phi=state.phi, psi=state.psi, order=order, k=state.k)
+    am, bm, cm, dm, c, s = resplit(state.phi, state.psi, prm.eps_s, prm.tau_deg, keep)
     state.logacc += 2.0 ** (-state.k) * math.log(c)
     rec["c"] = c
     rec["s"] = s.copy()
@@ -450,10 +462,12 @@ def rg_step(state, axis, prm, method):
     cc = _to_step_order(cm, dims, order)
     dd = _to_step_order(dm, dims, order)
     x, sig, y = bond_swap(b, cc, prm, state.k, rec)
+    if keep is not None:
+        keep.update(am=am, dm=dm, c=c, s=s, a=a, b=b, cc=cc, dd=dd, x=x, sig=sig, y=y)
     if method == "atrg":
-        gnew, hnew = atrg_coarse(a, x, sig, y, dd, prm, rec)
+        gnew, hnew = atrg_coarse(a, x, sig, y, dd, prm, rec, keep)
     else:
-        gnew, hnew = triad_coarse(a, x, sig, y, dd, prm, rec)
+        gnew, hnew = triad_coarse(a, x, sig, y, dd, prm, rec, keep)
     inv = list(np.argsort(order)) + [d]
     state.phi = np.ascontiguousarray(np.transpose(gnew, inv))
     state.psi = np.ascontiguousarray(np.transpose(hnew, inv))

@@ -1,0 +1,86 @@
+"""Pins of the oracle's impurity-tensor derivatives (Sec. III D).
+
+* Untruncated tori: the first two steps at D = 16 (and the initial tensor)
+  truncate nothing, so d(log Z/V)/d(beta) and d(log Z/V)/dh must equal the
+  Boltzmann averages <sum s s>/V and <sum s>/V of the enumerated torus.
+* beta = 0: m = tanh h exactly, at any step.
+* 2D thermodynamic limit: the internal energy of ATRG at D = 8 equals
+  Onsager's closed form within the truncation error of the flow (measured
+  3.6e-5 at beta = 0.3 and 7e-5 at 0.6), the closed form itself checked
+  against the derivative of the pinned Onsager free energy; in the ordered
+  phase the field derivative is Yang's spontaneous magnetisation.
+* 4D, high temperature: the impurity energy agrees with a central difference
+  of the same truncated flow and with the high-temperature series to the
+  truncation level, and the field derivative vanishes at h = 0.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import trg, impurity
+from oracle.ising import enumerate_derivatives_per_site, hte_4d, onsager_energy, onsager_log_z_1d
+
+
+@pytest.mark.parametrize("method", ["triad", "atrg"])
+@pytest.mark.parametrize("h", [0.0, 0.15])
+def test_exact_tori(method, h):
+    beta = 0.1497
+    ist = impurity.ImpurityState(beta, h, 4)
+    ref = enumerate_derivatives_per_site(beta, h, (1, 1, 1, 1))
+    assert np.allclose(impurity.derivatives(ist), ref, rtol=1e-13, atol=1e-14)
+    prm = trg.Params(D=16, seed=3)
+    for nst, ext in [(1, (2, 1, 1, 1)), (2, (2, 2, 1, 1))]:
+        impurity.step(ist, nst - 1, prm, method)
+        ref = enumerate_derivatives_per_site(beta, h, ext)
+        got = impurity.derivatives(ist)
+        assert abs(got[0] - ref[0]) < 1e-12 * abs(ref[0]), (got, ref)
+        assert abs(got[1] - ref[1]) < 1e-12 + 1e-12 * abs(ref[1]), (got, ref)
+
+
+def test_beta_zero_magnetisation():
+    h = 0.3
+    ist = impurity.ImpurityState(0.0, h, 4, wrt=("h",))
+    prm = trg.Params(D=4, seed=2)
+    for i in range(8):
+        impurity.step(ist, i % 4, prm, "triad")
+        assert abs(impurity.derivatives(ist)[0] - math.tanh(h)) < 1e-14
+
+
+def test_onsager_energy_closed_form():
+    for beta in (0.2, 0.3, 0.6):
+        e = 1e-5
+        fd = (onsager_log_z_1d(beta + e) - onsager_log_z_1d(beta - e)) / (2 * e)
+        assert abs(onsager_energy(beta) + fd) < 1e-8
+
+
+@pytest.mark.parametrize("beta,tol", [(0.3, 1e-4), (0.6, 2e-4)])
+def test_two_dimensional_energy_and_magnetisation(beta, tol):
+    prm = trg.Params(D=8, seed=4)
+    (db, dh), _ = impurity.run(beta, 0.0, prm, 40, "atrg", d=2)
+    assert abs(-db - onsager_energy(beta)) < tol
+    if beta < 0.4407:
+        assert abs(dh) < 1e-6          # disordered: no magnetisation
+    else:
+        # ordered: the truncated flow settles in one of the two ground states,
+        # and |m| is Yang's spontaneous magnetisation (1 - sinh(2b)^-4)^(1/8)
+        assert abs(abs(dh) - (1 - math.sinh(2 * beta) ** -4) ** 0.125) < 1e-4
+
+
+def test_four_dimensional_high_temperature():
+    # beta = 0.02: the flow's own derivative (central difference) and the
+    # impurity energy agree to the truncation level, and both sit within the
+    # D = 6 truncation error of the high-temperature series (through t^8,
+    # remainder ~1e-10 here)
+    beta = 0.02
+    prm = trg.Params(D=6, seed=8)
+    (db, dh), _ = impurity.run(beta, 0.0, prm, 24, "triad")
+    d = 1e-5
+    fp, _ = trg.run(beta + d, 0.0, prm, 24, "triad")
+    fm, _ = trg.run(beta - d, 0.0, prm, 24, "triad")
+    fb = (fp - fm) / (2 * d)
+    hb = (hte_4d(beta + d) - hte_4d(beta - d)) / (2 * d)
+    assert abs(db - fb) < 1e-4 * abs(fb), (db, fb)
+    assert abs(db - hb) < 2e-3 * abs(hb), (db, hb)
+    # the Gaussian sketch respects the spin-flip symmetry only to rounding
+    assert abs(dh) < 1e-8
