@@ -61,6 +61,106 @@ def cpu_baseline(D, r, beta, h, seed):
                           r * d0, t_step, threads, D, scale)}
 
 
+def batch_main(args):
+    """The 128-instance parameter scan (the T_c search workload): beta_j = 0.140 + 0.020 j / 31
+    (j = 0..31) x h_l in {0, 1e-4, 1e-3, 1e-2}, instance i = j + 32 l, D = (8, 12, 16, 24)[i mod 4],
+    r = 7, L = 2^10 per axis (40 steps).  One trg_batch_run against lone solves of a sample of the
+    instances (bit-for-bit equality checked), and the sequential time of all 128 estimated from
+    the sample's per-D step times."""
+    import numpy as np
+    import paper_2507_21909_amd as trg
+    seed = 0x2507219090000000 + 4000
+    betas, hs, Ds = [], [], []
+    for i in range(128):
+        j, l = i % 32, i // 32
+        betas.append(0.140 + 0.020 * j / 31)
+        hs.append([0.0, 1e-4, 1e-3, 1e-2][l])
+        Ds.append([8, 12, 16, 24][i % 4])
+    nsteps = args.batch_steps
+    b = trg.Batch(betas, hs, Ds, seed=seed)
+    print("batch of 128 created", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    b.run(nsteps)
+    got = b.log_z_per_site()
+    t_batch = time.perf_counter() - t0
+    print("batch run done in %.1f s" % t_batch, file=sys.stderr, flush=True)
+    b.close()
+    sample = [0, 1, 2, 3, 45, 46, 47, 60, 66, 79, 93, 98, 103, 113, 126, 127]
+    t_by_d = {}
+    for i in sample:
+        s = trg.Solver(seed=seed, instance=i)
+        s.tensor_init(trg.MODEL_ISING, betas[i], hs[i], Ds[i])
+        t0 = time.perf_counter()
+        for k in range(nsteps):
+            s.triad_atrg_step(k % 4)
+        f = s.log_z_per_site()
+        t_by_d.setdefault(Ds[i], []).append(time.perf_counter() - t0)
+        s.close()
+        if f != got[i]:
+            print("instance %d differs: batch %.17g alone %.17g" % (i, got[i], f), file=sys.stderr)
+            sys.exit(1)
+    t_seq = sum(32 * float(np.mean(v)) for v in t_by_d.values())
+    out = {"metric": "batched triad-ATRG instance-steps/s (128 instances, D in {8,12,16,24})",
+           "value": 128 * nsteps / t_batch, "unit": "instance-steps/s", "n_gpus": 1, "steps": nsteps,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic (4D Ising tensors from beta, h)",
+           "config": {"workload": "128-instance beta x h scan, r=7, %d steps" % nsteps},
+           "batch_wall_s": t_batch, "sequential_wall_s_estimated": t_seq,
+           "sequential_instance_steps_per_s": 128 * nsteps / t_seq,
+           "sequential_s_per_solve_by_D": {str(k): float(np.mean(v)) for k, v in sorted(t_by_d.items())},
+           "bitwise_equal_sample": len(sample)}
+    print(json.dumps(out), flush=True)
+
+
+def derivative_main(args):
+    """Internal energy and magnetisation over a beta scan by the impurity tangents: D = 24
+    (R = 168), L = 2^10 per axis (40 steps), beta_j = 0.148 + 0.003 j / 15 (j = 0..15), h = 1e-5,
+    contractions in the chosen precision.  For each beta: u = -d(log Z/V)/d(beta) and
+    m = d(log Z/V)/dh from one forward run carrying both tangents, the central differences of
+    the same flow (delta_beta = 1e-4, delta_h = h / 2, so h - delta_h keeps h's sign), and the
+    cost of the tangents as (time with tangents) / (time without)."""
+    import numpy as np
+    import paper_2507_21909_amd as trg
+    prec = {"fp64": trg.FP64, "fp32": trg.FP32, "bf16x3": trg.BF16X3}[args.precision]
+    seed = 0x2507219090000000 + 5000
+    D, nsteps, h = args.D, 40, 1e-5
+    rows = []
+
+    def flow(beta, hh, tangents):
+        s = trg.Solver(seed=seed, precision=prec, tangents=tangents)
+        s.tensor_init(trg.MODEL_ISING, beta, hh, D)
+        t0 = time.perf_counter()
+        for k in range(nsteps):
+            s.triad_atrg_step(k % 4)
+        f = s.log_z_per_site()
+        t = time.perf_counter() - t0
+        d = s.impurity_derivatives() if tangents else (None, None)
+        s.close()
+        return f, d, t
+
+    for j in range(args.derivative_points):
+        beta = 0.148 + 0.003 * j / 15
+        f, (db, dh), t_tan = flow(beta, h, trg.TAN_BETA | trg.TAN_H)
+        _, _, t_plain = flow(beta, h, 0)
+        fbp, _, _ = flow(beta + 1e-4, h, 0)
+        fbm, _, _ = flow(beta - 1e-4, h, 0)
+        fhp, _, _ = flow(beta, h + h / 2, 0)
+        fhm, _, _ = flow(beta, h - h / 2, 0)
+        ufd, mfd = -(fbp - fbm) / 2e-4, (fhp - fhm) / h
+        rows.append({"beta": beta, "log_z": f, "u": -db, "m": dh, "u_fd": ufd, "m_fd": mfd,
+                     "t_with_tangents_s": t_tan, "t_plain_s": t_plain})
+        print("beta %.5f  u %.10f (fd %.10f)  m %.6e (fd %.6e)  tangents/plain %.2f" % (
+            beta, -db, ufd, dh, mfd, t_tan / t_plain), file=sys.stderr, flush=True)
+    ratio = float(np.mean([r["t_with_tangents_s"] / r["t_plain_s"] for r in rows]))
+    out = {"metric": "impurity derivatives of log Z/V over a beta scan (D=%d)" % D,
+           "value": ratio, "unit": "time with both tangents / time without", "n_gpus": 1, "steps": nsteps,
+           "higher_is_better": False, "dtype": DTYPE[args.precision], "data": "synthetic (4D Ising)",
+           "config": {"workload": "triad-ATRG D=%d, r=7, 40 steps, h=1e-5, %d beta values in [0.148, 0.151]" % (
+               D, len(rows))},
+           "max_rel_u_vs_fd": max(abs(r["u"] - r["u_fd"]) / abs(r["u_fd"]) for r in rows),
+           "points": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,12 +172,23 @@ def main():
     ap.add_argument("--h", type=float, default=0.0)
     ap.add_argument("--precision", default="fp64", choices=list(PEAK))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", action="store_true", help="run the 128-instance scan instead of the D=32 step")
+    ap.add_argument("--batch-steps", type=int, default=40)
+    ap.add_argument("--derivatives", action="store_true",
+                    help="internal energy / magnetisation scan by the impurity tangents (use --D 24)")
+    ap.add_argument("--derivative-points", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the RG step on a single MI355X "
               "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.batch:
+        batch_main(args)
+        return
+    if args.derivatives:
+        derivative_main(args)
+        return
     import paper_2507_21909_amd as trg
     prec = {"fp64": trg.FP64, "fp32": trg.FP32, "bf16x3": trg.BF16X3}[args.precision]
     seed = 0x2507219090000000 + 3000

@@ -54,6 +54,9 @@ extern "C" {
 #define TRG_BF16X3 2   /* coarse-graining contractions as split BF16 MFMA, 3 products, FP32 acc.   */
 #define TRG_BF16X6 3   /* same with the 6 split products i + j <= 2 (about FP32 accuracy)          */
 
+#define TRG_TAN_BETA 1   /* carry d/dbeta of the site tensor (needs beta > 0)                     */
+#define TRG_TAN_H    2   /* carry d/dh of the site tensor                                          */
+
 #define TRG_SVD_SKETCH 0  /* bond swap by the randomized SVD of App. A (power_iters passes)         */
 #define TRG_SVD_EXACT  1  /* bond swap by the exact SVD of the QR-reduced core of App. A            */
 
@@ -72,11 +75,18 @@ typedef struct trg_options {
     int device;         /* HIP device ordinal                                                      */
     double tau_deg;     /* multiplet tolerance of every truncation and canonical basis, relative
                            to the largest value (0: default 1e-9); see kept-count rule           */
+    int tangents;       /* impurity tangents carried by triad_atrg_step (Sec. III D):
+                           TRG_TAN_BETA | TRG_TAN_H (0: none); see impurity_derivatives     */
+    int r_bond;         /* bond-swap overspanning of ILO triad-ATRG (Sec. II C, App. A): the bond
+                           swap keeps r_bond * D values, which the next step's alpha and beta
+                           carry; 1 is the plain bond swap.  Needs sketch_mult >= r_bond (the
+                           paper oversamples with sketch_mult = r_bond + 1), r_bond * D <= 256
+                           and sketch_mult * D <= 512 (tensor_init: TRG_E_UNSUPPORTED)          */
 } trg_options;
 
 /* Fills *opt with the defaults: dim 4, r 7, sketch_mult 2, power_iters 1,
  * seed 0, instance 0, FP64, sketch, max_sweeps 300, no cap, NULL stream,
- * device 0, tau_deg 1e-9. */
+ * device 0, tau_deg 1e-9, no tangents, r_bond 1. */
 void trg_default_options(trg_options *opt);
 
 typedef struct trg_state trg_state;
@@ -122,6 +132,43 @@ int triad_atrg_step(trg_state *s, int axis);
  */
 int log_z_per_site(trg_state *s, double *out);
 
+/*
+ * gu_wen_x -- the dimensionless ratio X = (Tr A)^2 / Tr(A A) of Sec. III D,
+ * A[k, l] = sum of the current coarse tensor T over every forward/backward
+ * leg pair traced except those along `axis` (k forward, l backward; the
+ * paper keeps the fourth leg open: axis = 3).  X counts the ground-state
+ * degeneracy: 2 in the ordered phase (h = 0), 1 in the disordered phase, so
+ * its jump over a beta scan locates T_c.  Computed on the device (one
+ * contraction over D^(d-1) chi entries, fixed-order sums); synchronises and
+ * writes one double to *out (host).  TRG_E_INVALID for a bad axis,
+ * TRG_E_STATE before tensor_init, TRG_E_NUMERICAL if Tr(A A) <= 0.
+ */
+int gu_wen_x(trg_state *s, int axis, double *out);
+
+/*
+ * impurity_derivatives -- d(log Z/V)/d(beta) and d(log Z/V)/dh of the torus the
+ * state represents, by the impurity-tensor method (Sec. III D): the derivative
+ * of the site tensor, summed over the sites, is carried through every step
+ * with the pure flow's truncations (triad isometries, squeezers, norms) held,
+ * the re-split and bond-swap tangents taken in the tangent space of the
+ * rank-chi matrices; then d(log Z/V) = 2^-n Tr dT^(n) / Tr T^(n).  Exact
+ * where nothing is truncated; otherwise it differs from the derivative of
+ * the truncated flow by terms of the order of the truncation.  The internal
+ * energy per site is u = -(*dbeta) and the magnetisation m = *dh.
+ * The state must be created with opt.tangents; each output pointer (host,
+ * may be NULL) receives its derivative, or NaN if that tangent is not
+ * carried.  Synchronises.  TRG_E_STATE without tangents or before
+ * tensor_init, TRG_E_NUMERICAL if the trace is not positive.
+ */
+int impurity_derivatives(trg_state *s, double *dbeta, double *dh);
+
+/*
+ * trg_release_workspace -- frees the state's step workspace (the device
+ * arena that a step's temporaries live in; the next step allocates it
+ * again).  The state tensors stay.  Synchronises the state's stream first.
+ */
+int trg_release_workspace(trg_state *s);
+
 /* ---- many instances ------------------------------------------------------ */
 
 typedef struct trg_batch trg_batch;
@@ -140,7 +187,9 @@ int trg_batch_create(int n, const double *betas, const double *hs, const int *Ds
  * trg_batch_run -- nsteps triad-ATRG steps on every instance, along
  * axes[0..nsteps) (NULL: 0, 1, 2, 3, 0, ...).  Host workers (up to 8) run
  * instances concurrently on their own streams; each instance gives the same
- * bits as a lone solver with the same options.  Returns after all steps are
+ * bits as a lone solver with the same options.  An instance's step workspace
+ * is released when its steps are done, so the device holds at most one
+ * workspace per worker besides the instances' state tensors.  Returns after all steps are
  * issued and their host read-backs done; the first error code of any
  * instance is returned (trg_batch_last_error names the instance).
  */
@@ -200,6 +249,7 @@ int trg_qr_noalloc(const double *A, int64_t m, int n, double *Q, double *R, void
 #define TRG_T_PHI    0   /* Phi  [dims..., chi], natural axis order, FP64 */
 #define TRG_T_PSI    1   /* Psi  [dims..., chi]                           */
 #define TRG_T_SIGMA  2   /* bond-swap singular values of the last step    */
+#define TRG_T_RESPLIT 3  /* re-split singular values / c_k of the last step */
 
 /* Shape of the current state: dims[0..dim-1] leg dims, *chi the bond. */
 int trg_shape(trg_state *s, int *dims, int *chi, int *steps);

@@ -6,8 +6,10 @@ library is missing: there is no CPU fallback.
 """
 from .binding import (Solver, Batch, TrgError, load_library, selftest_gemm, selftest_tsqr, selftest_svd, selftest_eigh,
                       selftest_pchol, selftest_gram_eig,
-                      selftest_sketch, qr, qr_noalloc, FP64, FP32, BF16X3, BF16X6, SVD_SKETCH, SVD_EXACT, MODEL_ISING)
+                      selftest_sketch, qr, qr_noalloc, FP64, FP32, BF16X3, BF16X6, SVD_SKETCH, SVD_EXACT, MODEL_ISING,
+                      T_PHI, T_PSI, T_SIGMA, T_RESPLIT, TAN_BETA, TAN_H)
 
 __all__ = ["Solver", "Batch", "TrgError", "load_library", "selftest_gemm", "selftest_tsqr", "selftest_svd", "selftest_eigh",
            "selftest_pchol", "selftest_gram_eig",
-           "selftest_sketch", "qr", "qr_noalloc", "FP64", "FP32", "BF16X3", "BF16X6", "SVD_SKETCH", "SVD_EXACT", "MODEL_ISING"]
+           "selftest_sketch", "qr", "qr_noalloc", "FP64", "FP32", "BF16X3", "BF16X6", "SVD_SKETCH", "SVD_EXACT", "MODEL_ISING",
+           "T_PHI", "T_PSI", "T_SIGMA", "T_RESPLIT", "TAN_BETA", "TAN_H"]

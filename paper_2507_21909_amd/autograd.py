@@ -1,29 +1,42 @@
 """log Z/V of the 4D Ising model by triad-ATRG as a torch.autograd.Function.
 
 forward(beta, h) runs the RG flow on the GPU (the C ABI, on torch's current
-stream) and returns log Z/V; backward returns (d/dbeta, d/dh) log Z/V, i.e.
-minus the internal energy per site and the magnetisation per site with the
-field entering as exp(h s).
+stream) and returns log Z/V; backward returns grad * (d/dbeta, d/dh) log Z/V,
+i.e. minus the internal energy per site and the magnetisation per site (the
+field enters as exp(h s)).
 
-The derivatives are central differences of the same deterministic flow (same
-seed, so the same sketches): 2 extra solves per variable.  The steps of h
-stay inside h's sign (delta_h <= |h| / 2 when h != 0), because for beta above
-the critical coupling log Z/V has a kink at h = 0.
+The derivatives come from the same forward run: the solver carries the
+impurity tangents of the site tensor (impurity_derivatives in the C ABI,
+Sec. III D) through every step, so backward costs no further solve.  They
+are exact where no truncation acts and differ from the derivative of the
+truncated flow by terms of the order of the truncation.  The beta tangent
+needs beta > 0 (the CP factor sqrt(sinh beta) is not differentiable at 0);
+at beta = 0 the beta derivative is the closed form 4 tanh(h)^2 of
+independent spins.
 """
+import math
+
 import torch
 
-from .binding import Solver, FP64
+from .binding import Solver, FP64, TAN_BETA, TAN_H
 
 
-def _log_z(beta, h, D, nsteps, seed, r, precision, tau_deg, stream):
-    s = Solver(seed=seed, r=r, precision=precision, tau_deg=tau_deg, stream=stream)
+def solve(beta, h, D, nsteps, seed=0, r=7, precision=FP64, tau_deg=0.0, stream=None, tangents=TAN_BETA | TAN_H):
+    """(log Z/V, d/dbeta, d/dh) of an nsteps triad-ATRG flow (axes cycling 0..3)."""
+    if beta == 0.0:
+        tangents &= ~TAN_BETA
+    s = Solver(seed=seed, r=r, precision=precision, tau_deg=tau_deg, stream=stream, tangents=tangents)
     try:
         s.tensor_init(0, float(beta), float(h), D)
         for k in range(nsteps):
             s.triad_atrg_step(k % 4)
-        return s.log_z_per_site()
+        f = s.log_z_per_site()
+        db, dh = s.impurity_derivatives() if tangents else (math.nan, math.nan)
     finally:
         s.close()
+    if beta == 0.0:
+        db = 4.0 * math.tanh(h) ** 2
+    return f, db, dh
 
 
 def _stream():
@@ -33,35 +46,19 @@ def _stream():
 
 
 class TriadFreeEnergy(torch.autograd.Function):
-    """log Z/V (beta, h) with derivatives; see the module docstring."""
+    """log Z/V (beta, h) with impurity-tensor derivatives; see the module docstring."""
 
     @staticmethod
-    def forward(ctx, beta, h, D=8, nsteps=40, seed=0, r=7, precision=FP64, tau_deg=0.0, delta_beta=1e-4,
-                delta_h=1e-4):
+    def forward(ctx, beta, h, D=8, nsteps=40, seed=0, r=7, precision=FP64, tau_deg=0.0):
         b, hv = float(beta), float(h)
-        st = _stream()
-        f = _log_z(b, hv, D, nsteps, seed, r, precision, tau_deg, st)
-        ctx.args = (b, hv, D, nsteps, seed, r, precision, tau_deg, delta_beta, delta_h)
-        return torch.tensor(f, dtype=torch.float64, device=beta.device if torch.is_tensor(beta) else None)
+        f, db, dh = solve(b, hv, D, nsteps, seed, r, precision, tau_deg, _stream())
+        ctx.grads = (db, dh)
+        dev = beta.device if torch.is_tensor(beta) else None
+        return torch.tensor(f, dtype=torch.float64, device=dev)
 
     @staticmethod
     def backward(ctx, grad):
-        b, hv, D, nsteps, seed, r, precision, tau_deg, db, dh = ctx.args
-        st = _stream()
-
-        def f(x, y):
-            return _log_z(x, y, D, nsteps, seed, r, precision, tau_deg, st)
-
-        gb = gh = None
-        if ctx.needs_input_grad[0]:
-            d = min(db, b) if b > 0 else db          # beta stays >= 0
-            if b - d < 0:
-                gb = (f(b + d, hv) - f(b, hv)) / d
-            else:
-                gb = (f(b + d, hv) - f(b - d, hv)) / (2 * d)
-        if ctx.needs_input_grad[1]:
-            d = min(dh, abs(hv) / 2) if hv != 0 else dh
-            gh = (f(b, hv + d) - f(b, hv - d)) / (2 * d)
-        out_b = None if gb is None else grad * torch.tensor(gb, dtype=torch.float64, device=grad.device)
-        out_h = None if gh is None else grad * torch.tensor(gh, dtype=torch.float64, device=grad.device)
-        return (out_b, out_h) + (None,) * 8
+        db, dh = ctx.grads
+        out_b = grad * torch.tensor(db, dtype=torch.float64, device=grad.device) if ctx.needs_input_grad[0] else None
+        out_h = grad * torch.tensor(dh, dtype=torch.float64, device=grad.device) if ctx.needs_input_grad[1] else None
+        return (out_b, out_h) + (None,) * 6

@@ -13,8 +13,9 @@ LIB_PATH = os.path.join(HERE, "libtrg.so")
 
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 SVD_SKETCH, SVD_EXACT = 0, 1
+TAN_BETA, TAN_H = 1, 2
 MODEL_ISING = 0
-T_PHI, T_PSI, T_SIGMA = 0, 1, 2
+T_PHI, T_PSI, T_SIGMA, T_RESPLIT = 0, 1, 2, 3
 
 
 class Options(ctypes.Structure):
@@ -32,6 +33,8 @@ class Options(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("device", ctypes.c_int),
         ("tau_deg", ctypes.c_double),
+        ("tangents", ctypes.c_int),
+        ("r_bond", ctypes.c_int),
     ]
 
 
@@ -63,6 +66,8 @@ def load_library(path=None):
     lib.atrg_step.argtypes = [st, ctypes.c_int]
     lib.triad_atrg_step.argtypes = [st, ctypes.c_int]
     lib.log_z_per_site.argtypes = [st, _DP]
+    lib.gu_wen_x.argtypes = [st, ctypes.c_int, _DP]
+    lib.impurity_derivatives.argtypes = [st, _DP, _DP]
     lib.trg_shape.argtypes = [st, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                               ctypes.POINTER(ctypes.c_int)]
     lib.trg_export.argtypes = [st, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t]
@@ -97,7 +102,8 @@ def load_library(path=None):
     lib.trg_qr_noalloc.restype = ctypes.c_int
     for f in ("trg_batch_create", "trg_batch_run", "trg_batch_log_z", "trg_batch_size", "trg_batch_destroy"):
         getattr(lib, f).restype = ctypes.c_int
-    for f in ("trg_create", "trg_destroy", "tensor_init", "atrg_step", "triad_atrg_step", "log_z_per_site",
+    for f in ("trg_create", "trg_destroy", "tensor_init", "atrg_step", "triad_atrg_step", "log_z_per_site", "gu_wen_x",
+              "impurity_derivatives",
               "trg_shape", "trg_export", "trg_set_timing", "trg_kernel_time", "trg_selftest_gemm",
               "trg_selftest_tsqr", "trg_selftest_svd", "trg_selftest_eigh", "trg_selftest_pchol",
               "trg_selftest_gram_eig", "trg_selftest_sketch"):
@@ -121,7 +127,8 @@ class Solver:
     """One ATRG / triad-ATRG solve on one GPU (a trg_state)."""
 
     def __init__(self, dim=4, r=7, sketch_mult=2, power_iters=1, seed=0, instance=0, precision=FP64,
-                 bond_svd=SVD_SKETCH, max_sweeps=0, workspace_cap=0, stream=None, device=0, tau_deg=0.0):
+                 bond_svd=SVD_SKETCH, max_sweeps=0, workspace_cap=0, stream=None, device=0, tau_deg=0.0,
+                 r_bond=1, tangents=0):
         lib = load_library()
         o = Options()
         lib.trg_default_options(ctypes.byref(o))
@@ -130,6 +137,8 @@ class Solver:
         o.max_sweeps, o.workspace_cap, o.device = max_sweeps, workspace_cap, device
         o.stream = stream
         o.tau_deg = tau_deg
+        o.r_bond = r_bond
+        o.tangents = tangents
         self._lib = lib
         self._s = ctypes.c_void_p()
         _check(lib.trg_create(ctypes.byref(o), ctypes.byref(self._s)))
@@ -158,6 +167,19 @@ class Solver:
     def log_z_per_site(self):
         out = ctypes.c_double()
         _check(self._lib.log_z_per_site(self._s, ctypes.byref(out)), self._s)
+        return out.value
+
+    def impurity_derivatives(self):
+        """(d(log Z/V)/d(beta), d(log Z/V)/dh) by the impurity-tensor method (Sec. III D); NaN for a
+        tangent the solver does not carry.  u = -first, m = second."""
+        db, dh = ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.impurity_derivatives(self._s, ctypes.byref(db), ctypes.byref(dh)), self._s)
+        return db.value, dh.value
+
+    def gu_wen_x(self, axis=3):
+        """X = (Tr A)^2 / Tr(A A) of the current coarse tensor, A open along ``axis`` (Sec. III D)."""
+        out = ctypes.c_double()
+        _check(self._lib.gu_wen_x(self._s, axis, ctypes.byref(out)), self._s)
         return out.value
 
     def shape(self):

@@ -98,6 +98,7 @@ int trg_batch_run(trg_batch *b, int nsteps, const int *axes) {
                     break;
                 }
             }
+            (void)trg_release_workspace(b->s[i]);   // bounded memory: one workspace per worker
         }
     };
     std::vector<std::thread> pool;

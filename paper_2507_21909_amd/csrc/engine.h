@@ -20,6 +20,8 @@ class Arena {
     Mark mark() const;
     void release(const Mark &m);
     void reset() { release(Mark{0, 0}); }
+    // frees every chunk (no allocation may be live, nor any kernel using one)
+    void trim();
     size_t held() const { return total_; }
     void set_cap(size_t c) { cap_ = c; }
 

@@ -47,6 +47,13 @@ void *Arena::alloc(size_t bytes) {
     return p;
 }
 
+void Arena::trim() {
+    for (auto &c : chunks_) (void)hipFree(c.base);
+    chunks_.clear();
+    cur_ = 0;
+    total_ = 0;
+}
+
 Arena::Mark Arena::mark() const {
     if (chunks_.empty()) return Mark{0, 0};
     return Mark{cur_, chunks_[cur_].used};

@@ -27,10 +27,17 @@ struct trg_state {
     double beta = 0.0, h = 0.0;
     std::vector<int> dims;
     double *phi = nullptr, *psi = nullptr;   // persistent state
+    // impurity tangents (dPhi, dPsi) of d/dbeta and d/dh, when opt.tangents asks for them
+    int ntan = 0, tan_kind[2] = {0, 0};
+    double *dphi[2] = {nullptr, nullptr}, *dpsi[2] = {nullptr, nullptr};
+    size_t cap_tan = 0;
     size_t cap_state = 0;
-    double *dscal = nullptr;   // [0] logacc, [1] trace, [3] logacc before the step, [1024..2048) trace partials
+    double *dscal = nullptr;   // [0] logacc, [1] trace, [3] logacc before the step, [4..6) Gu-Wen traces,
+                               // [6] norm c_k of the last re-split, [8..11) impurity traces,
+                               // [1024..2048) trace partials
     int *dint = nullptr;       // [0] numerical status, [1] status before the step, [8..] kept counts
-    std::vector<double> sigma_last;
+    std::vector<double> sigma_last;    // bond-swap singular values of the last step
+    std::vector<double> resplit_last;  // re-split singular values / c_k of the last step
     std::string err;
     bool timing = false;
     double t_ms = 0.0, t_flops = 0.0;
@@ -46,13 +53,14 @@ constexpr double EPS_S = 1e-14, EPS_LAM = 1e-14, EPS_SQ = 1e-14, TAU_DEG_DEFAULT
 constexpr double PCHOL_TOL = 2.220446049250313e-16;
 
 // ---------------------------------------------------------------- small kernels
-__global__ void resplit_norm_kernel(double *s, int n, int k, double *logacc, double eps, int *status) {
+__global__ void resplit_norm_kernel(double *s, int n, int k, double *logacc, double eps, int *status, double *cout) {
     if (threadIdx.x || blockIdx.x) return;
     double c = s[0];
     if (!(c > 0.0) || !isfinite(c)) {
         *status = 1;
         c = 1.0;
     }
+    *cout = c;
     *logacc += ldexp(log(c), -k);
     for (int i = 0; i < n; ++i) {
         double v = s[i] / c;
@@ -68,6 +76,32 @@ __global__ void sprime_kernel(const double *rot, const double *s, int n, double 
     double acc = 0.0;
     for (int k = 0; k < n; ++k) acc += rot[(long)k * n + r] * s[k] * rot[(long)k * n + c];
     sp[i] = acc;
+}
+
+// S'^+ = R^T diag(s^+) R with s^+ = 1/s on the kept values, 0 elsewhere
+__global__ void sprime_inv_kernel(const double *rot, const double *s, int n, double *sp) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * n) return;
+    int r = i / n, c = i % n;
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double si = s[k] > 0.0 ? 1.0 / s[k] : 0.0;
+        acc += rot[(long)k * n + r] * si * rot[(long)k * n + c];
+    }
+    sp[i] = acc;
+}
+
+// y = (y + a x) * scale, scale = 1 / *cinv_of when cinv_of is given
+__global__ void axpy_scale_kernel(double *y, const double *x, long n, double a, const double *cinv_of) {
+    const double sc = cinv_of ? 1.0 / *cinv_of : 1.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        y[i] = (y[i] + (x ? a * x[i] : 0.0)) * sc;
+}
+
+// out[j] = 1 / v[j] for v[j] > 0, else 0
+__global__ void inv_pos_kernel(const double *v, double *out, int n) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) out[j] = v[j] > 0.0 ? 1.0 / v[j] : 0.0;
 }
 
 __global__ void mask_sign_kernel(double *sg, const double *s, int n) {
@@ -133,6 +167,32 @@ __global__ void sum_kernel(const double *part, int n, double *out) {
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = red[0];
+}
+
+// Gu-Wen traces of A (n x n, row-major): out[0] = Tr A, out[1] = Tr(A A) =
+// sum_{k,l} A[k,l] A[l,k]; one workgroup, fixed summation order
+__global__ void gu_wen_kernel(const double *a, int n, double *out) {
+    __shared__ double r1[256], r2[256];
+    double t1 = 0.0, t2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) t1 += a[(long)i * n + i];
+    for (long e = threadIdx.x; e < (long)n * n; e += 256) {
+        const long k = e / n, l = e % n;
+        t2 += a[e] * a[l * n + k];
+    }
+    r1[threadIdx.x] = t1;
+    r2[threadIdx.x] = t2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            r1[threadIdx.x] += r1[threadIdx.x + s];
+            r2[threadIdx.x] += r2[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = r1[0];
+        out[1] = r2[0];
+    }
 }
 
 inline unsigned g1(long n) { return (unsigned)std::max(1L, std::min((n + 255) / 256, 65536L)); }
@@ -235,6 +295,7 @@ bool gram_eig_pchol(Ctx &c, const double *k, int count, int n, int max_sweeps, d
 struct Split {
     DT A, B, C, Dm;   // step order [a, t1, t2, t3, chi]
     DT s;             // chi
+    DT a_nat, dm_nat, rot;   // natural order A, D as F x chi matrices; canonical rotation
 };
 
 Split resplit(Step &T, const std::vector<int> &order) {
@@ -244,7 +305,7 @@ Split resplit(Step &T, const std::vector<int> &order) {
     long F = 1;
     for (int v : S->dims) F *= v;
     const int chi = S->chi;
-    TRG_REQUIRE(chi <= 64, -6, "bond dimension above 64 not supported by the TSQR kernel");
+    TRG_REQUIRE(chi <= 512, -6, "bond dimension above 512 not supported by the QR");
     TRG_REQUIRE(F >= chi, -6, "re-split: fewer rows than columns");
     DT q1 = talloc(c, {(int)F, chi}), r1 = talloc(c, {chi, chi});
     DT q2 = talloc(c, {(int)F, chi}), r2 = talloc(c, {chi, chi});
@@ -254,7 +315,8 @@ Split resplit(Step &T, const std::vector<int> &order) {
     DT w = contract(c, r1, "ia", r2, "ja", "ij");
     DT s = talloc(c, {chi}), u = talloc(c, {chi, chi}), v = talloc(c, {chi, chi});
     svd_rowmajor(T, w, s.p, u.p, v.p);
-    hipLaunchKernelGGL(resplit_norm_kernel, dim3(1), dim3(1), 0, c.st, s.p, chi, S->k, S->dscal, EPS_S, S->dint);
+    hipLaunchKernelGGL(resplit_norm_kernel, dim3(1), dim3(1), 0, c.st, s.p, chi, S->k, S->dscal, EPS_S, S->dint,
+                       S->dscal + 6);
     DT A = contract(c, q1, "Fa", u, "ab", "Fb");
     DT Dm = contract(c, q2, "Fa", v, "ab", "Fb");
     // canonical bond basis: rotation within multiplets of s, B = Dm S', C = A S'
@@ -272,6 +334,10 @@ Split resplit(Step &T, const std::vector<int> &order) {
     hipLaunchKernelGGL(sprime_kernel, dim3(g1((long)chi * chi)), dim3(256), 0, c.st, rot.p, s.p, chi, sp.p);
     DT B2 = contract(c, D2, "Fa", sp, "ab", "Fb");
     DT C2 = contract(c, A2, "Fa", sp, "ab", "Fb");
+    Split o;
+    o.a_nat = A2;
+    o.dm_nat = D2;
+    o.rot = rot;
     // tensors in step order
     std::string nat, stp;
     for (int i = 0; i < d; ++i) nat += (char)('a' + i);
@@ -284,7 +350,6 @@ Split resplit(Step &T, const std::vector<int> &order) {
     D2.d = fd;
     B2.d = fd;
     C2.d = fd;
-    Split o;
     o.A = permuted(c, A2, nat, stp);
     o.Dm = permuted(c, D2, nat, stp);
     o.B = permuted(c, B2, nat, stp);
@@ -310,7 +375,7 @@ Swap bond_swap(Step &T, const Split &sp) {
     const long I = J;
     const long p = std::min(J, (long)x * chi), q = std::min(I, (long)x * chi);
     const long rowsN = chi * q, colsN = chi * p;
-    const int gcap = (int)std::min<long>(S->D, std::min(rowsN, colsN));
+    const int gcap = (int)std::min<long>((long)S->opt.r_bond * S->D, std::min(rowsN, colsN));
     const int m = S->opt.sketch_mult * S->D;
     const bool exact = S->opt.bond_svd == TRG_SVD_EXACT || m >= std::min(rowsN, colsN);
     // label strings: x, t legs (i j k / u v w), chi
@@ -322,7 +387,7 @@ Swap bond_swap(Step &T, const Split &sp) {
     std::vector<int> sdims;   // sign multi-index dims in GPU row order, with their weights
     if (exact) {
         const int nb = x * chi;
-        TRG_REQUIRE(nb <= 64 && J >= nb, -6, "exact bond swap: x*chi must be <= 64 and <= prod(transverse)");
+        TRG_REQUIRE(nb <= 512 && J >= nb, -6, "exact bond swap: x*chi must be <= 512 and <= prod(transverse)");
         DT Bp = permuted(c, Bt, "x" + tl + "a", tl + "xa");
         DT Cp = permuted(c, Ct, "x" + tl + "b", tl + "xb");
         DT qb = talloc(c, {(int)J, nb}), rb = talloc(c, {nb, nb});
@@ -747,7 +812,12 @@ DT coarse_half(Step &T, const DT &em, const DT &fp, const DT &t23) {
     return out;
 }
 
-void triad_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi) {
+// pieces of a triad step that the impurity tangents reuse (held fixed)
+struct TriadKeep {
+    DT UA, UX, UY, UD, M2, N2, f, hh, em, fp, ijmm, hn, gp, klnn;
+};
+
+void triad_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi, TriadKeep *keep = nullptr) {
     trg_state *S = T.S;
     Ctx &c = T.c;
     const int D = S->D;
@@ -820,6 +890,107 @@ void triad_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi) {
     DT hn = contract(c, hh, "xDsb", N[2], "tsc", "xDcbt");              // [x, kD, k3, beta, t]
     DT gp = permuted(c, g, "bYtg", "btYg");                             // [beta, t, kY, g]
     psi = coarse_half(T, hn, gp, klnn);
+    if (keep) *keep = TriadKeep{UA, UX, UY, UD, M[2], N[2], f, hh, em, fp, ijmm, hn, gp, klnn};
+}
+
+// ---------------------------------------------------------------- impurity tangents
+// y += a x, then y /= *cdev when cdev is given (all on the stream)
+void axpy_scale(Ctx &c, DT &y, const DT *x, double a, const double *cdev) {
+    hipLaunchKernelGGL(axpy_scale_kernel, dim3(g1(y.n())), dim3(256), 0, c.st, y.p, x ? x->p : nullptr, y.n(), a, cdev);
+    TRG_HIP_CHECK(hipGetLastError());
+}
+
+// One triad step of an impurity tangent (dPhi, dPsi) of the state: the pure
+// step's isometries, squeezers and norm are held; the re-split and bond-swap
+// tangents live in the tangent space of the rank-chi matrices (re-split gauge
+// A^T dA = 0, D^T dD = 0; bond swap d(X sigma) = dM Y, dY = (1 - Y Y^T) dM^T X
+// sigma^+).  Returns the new tangent in step order [x, k1, k2, k3, g].
+void triad_tangent(Step &T, const Split &sp, const Swap &sw, const TriadKeep &K, const double *dphi_p,
+                   const double *dpsi_p, const std::vector<int> &order, DT &dphi_out, DT &dpsi_out) {
+    trg_state *S = T.S;
+    Ctx &c = T.c;
+    const int d = (int)S->dims.size();
+    const int chi = S->chi;
+    long F = 1;
+    for (int v : S->dims) F *= v;
+    DT phi, psi, dphi, dpsi;
+    phi.p = S->phi;
+    psi.p = S->psi;
+    dphi.p = const_cast<double *>(dphi_p);
+    dpsi.p = const_cast<double *>(dpsi_p);
+    phi.d = psi.d = dphi.d = dpsi.d = {(int)F, chi};
+    const DT &a = sp.a_nat, &dm = sp.dm_nat;
+    const double *cdev = S->dscal + 6;
+    // re-split: Z1 = (dT/c) D, Z2 = (dT/c)^T A
+    DT w1 = contract(c, psi, "Fg", dm, "Fb", "gb");
+    DT w2 = contract(c, dpsi, "Fg", dm, "Fb", "gb");
+    DT z1 = contract(c, dphi, "Fg", w1, "gb", "Fb");
+    DT z1b = contract(c, phi, "Fg", w2, "gb", "Fb");
+    axpy_scale(c, z1, &z1b, 1.0, cdev);
+    DT v1 = contract(c, dphi, "Fg", a, "Fa", "ga");
+    DT v2 = contract(c, phi, "Fg", a, "Fa", "ga");
+    DT z2 = contract(c, psi, "Fg", v1, "ga", "Fa");
+    DT z2b = contract(c, dpsi, "Fg", v2, "ga", "Fa");
+    axpy_scale(c, z2, &z2b, 1.0, cdev);
+    DT spp = talloc(c, {chi, chi});
+    hipLaunchKernelGGL(sprime_inv_kernel, dim3(g1((long)chi * chi)), dim3(256), 0, c.st, sp.rot.p, sp.s.p, chi, spp.p);
+    // dA = (1 - A A^T) Z1 S'^+, dD = (1 - D D^T) Z2 S'^+, dC = Z1, dB = Z2
+    DT p1 = contract(c, a, "Fa", z1, "Fb", "ab");
+    DT q1 = contract(c, a, "Fa", p1, "ab", "Fb");
+    DT r1 = talloc(c, {(int)F, chi});
+    copy(r1.p, z1.p, r1.n(), c.st);
+    axpy_scale(c, r1, &q1, -1.0, nullptr);
+    DT da = contract(c, r1, "Fb", spp, "bc", "Fc");
+    DT p2 = contract(c, dm, "Fa", z2, "Fb", "ab");
+    DT q2 = contract(c, dm, "Fa", p2, "ab", "Fb");
+    DT r2 = talloc(c, {(int)F, chi});
+    copy(r2.p, z2.p, r2.n(), c.st);
+    axpy_scale(c, r2, &q2, -1.0, nullptr);
+    DT ddm = contract(c, r2, "Fb", spp, "bc", "Fc");
+    std::string nat, stp;
+    for (int i = 0; i < d; ++i) nat += (char)('a' + i);
+    for (int i = 0; i < d; ++i) stp += (char)('a' + order[i]);
+    nat += 'z';
+    stp += 'z';
+    std::vector<int> fd(S->dims.begin(), S->dims.end());
+    fd.push_back(chi);
+    da.d = ddm.d = z1.d = z2.d = fd;
+    DT dA = permuted(c, da, nat, stp), dDm = permuted(c, ddm, nat, stp);
+    DT dB = permuted(c, z2, nat, stp), dC = permuted(c, z1, nat, stp);
+    // bond swap: dM = dB C + B dC over the shared leg x
+    const DT &B = sp.B, &C = sp.C, &X = sw.X, &Y = sw.Y;
+    DT by = contract(c, B, "xijka", Y, "bijkh", "xabh");
+    DT dby = contract(c, dB, "xijka", Y, "bijkh", "xabh");
+    DT dxs = contract(c, C, "xuvwb", dby, "xabh", "auvwh");
+    DT dxs2 = contract(c, dC, "xuvwb", by, "xabh", "auvwh");
+    axpy_scale(c, dxs, &dxs2, 1.0, nullptr);                            // d(X sigma) = dM Y
+    DT cx = contract(c, C, "xuvwb", X, "auvwg", "xabg");
+    DT dcx = contract(c, dC, "xuvwb", X, "auvwg", "xabg");
+    DT dmx = contract(c, dB, "xijka", cx, "xabg", "bijkg");
+    DT dmx2 = contract(c, B, "xijka", dcx, "xabg", "bijkg");
+    axpy_scale(c, dmx, &dmx2, 1.0, nullptr);                            // dM^T X
+    const int ng = sw.sig.d[0];
+    DT sinv = talloc(c, {ng});
+    hipLaunchKernelGGL(inv_pos_kernel, dim3(g1(ng)), dim3(256), 0, c.st, sw.sig.p, sinv.p, ng);
+    scale_axis(dmx.p, dmx.d, 4, sinv.p, 1, c.st);
+    DT yty = contract(c, Y, "bijkh", dmx, "bijkg", "hg");
+    DT yyty = contract(c, Y, "bijkh", yty, "hg", "bijkg");
+    axpy_scale(c, dmx, &yyty, -1.0, nullptr);                           // dY = (1 - Y Y^T) dM^T X sigma^+
+    // triad tensors and makeMG / makeMH, one factor at a time
+    DT de = contract(c, dA, "xijta", K.UA, "ijk", "xkta");
+    DT df = contract(c, dxs, "aijtg", K.UX, "ijk", "aktg");
+    DT dg = contract(c, dmx, "bijtg", K.UY, "ijk", "bktg");
+    DT dh = contract(c, dDm, "xijtb", K.UD, "ijk", "xktb");
+    DT dem = contract(c, de, "xAta", K.M2, "tsc", "xAcas");
+    DT dfp = permuted(c, df, "aXsg", "asXg");
+    dphi_out = coarse_half(T, dem, K.fp, K.ijmm);
+    DT t2 = coarse_half(T, K.em, dfp, K.ijmm);
+    axpy_scale(c, dphi_out, &t2, 1.0, nullptr);
+    DT dhn = contract(c, dh, "xDsb", K.N2, "tsc", "xDcbt");
+    DT dgp = permuted(c, dg, "bYtg", "btYg");
+    dpsi_out = coarse_half(T, dhn, K.gp, K.klnn);
+    DT t3 = coarse_half(T, K.hn, dgp, K.klnn);
+    axpy_scale(c, dpsi_out, &t3, 1.0, nullptr);
 }
 
 // ---------------------------------------------------------------- one step
@@ -828,6 +999,8 @@ void do_step(trg_state *S, int axis, bool triad) {
     const int d = S->opt.dim;
     TRG_REQUIRE(axis >= 0 && axis < d, -1, "axis out of range");
     TRG_REQUIRE(d == 4, -6, "the GPU path implements d = 4");
+    TRG_REQUIRE(triad || S->ntan == 0, TRG_E_UNSUPPORTED,
+                "impurity tangents are carried by triad_atrg_step only (atrg_step: create the state without tangents)");
     S->ar.reset();
     Step T(S);
     // accumulator and status before the step (dscal[3], dint[1]); restored if the step fails
@@ -838,8 +1011,11 @@ void do_step(trg_state *S, int axis, bool triad) {
     Split sp = resplit(T, order);
     Swap sw = bond_swap(T, sp);
     DT phi, psi;
-    if (triad) triad_coarse(T, sp, sw, phi, psi);
+    TriadKeep keep;
+    if (triad) triad_coarse(T, sp, sw, phi, psi, S->ntan ? &keep : nullptr);
     else atrg_coarse(T, sp, sw, phi, psi);
+    DT dphi[2], dpsi[2];
+    for (int t = 0; t < S->ntan; ++t) triad_tangent(T, sp, sw, keep, S->dphi[t], S->dpsi[t], order, dphi[t], dpsi[t]);
     // back to natural axis order
     std::string stp, nat;
     for (int i = 0; i < d; ++i) stp += (char)('a' + order[i]);
@@ -848,9 +1024,10 @@ void do_step(trg_state *S, int axis, bool triad) {
     nat += 'z';
     TRG_REQUIRE((size_t)phi.n() <= S->cap_state && (size_t)psi.n() <= S->cap_state, -6, "state exceeds D^5");
     // numerical status of the step (norm, multiplet sizes) before the state is overwritten
-    std::vector<double> sig(sw.sig.d[0], 0.0);
+    std::vector<double> sig(sw.sig.d[0], 0.0), rsv(sp.s.d[0], 0.0);
     int status = 0;
     TRG_HIP_CHECK(hipMemcpyAsync(sig.data(), sw.sig.p, sizeof(double) * sig.size(), hipMemcpyDeviceToHost, S->st));
+    TRG_HIP_CHECK(hipMemcpyAsync(rsv.data(), sp.s.p, sizeof(double) * rsv.size(), hipMemcpyDeviceToHost, S->st));
     TRG_HIP_CHECK(hipMemcpyAsync(&status, S->dint, sizeof(int), hipMemcpyDeviceToHost, S->st));
     TRG_HIP_CHECK(hipStreamSynchronize(S->st));
     TRG_REQUIRE(status != 1, -4, "non-positive or non-finite norm at the re-split");
@@ -861,11 +1038,16 @@ void do_step(trg_state *S, int axis, bool triad) {
     for (int i = 0; i <= d; ++i) perm[i] = (int)stp.find(nat[i]);
     permute(phi.p, S->phi, phi.d, perm, S->st);
     permute(psi.p, S->psi, psi.d, perm, S->st);
+    for (int t = 0; t < S->ntan; ++t) {
+        permute(dphi[t].p, S->dphi[t], dphi[t].d, perm, S->st);
+        permute(dpsi[t].p, S->dpsi[t], dpsi[t].d, perm, S->st);
+    }
     std::vector<int> nd(d);
     for (int i = 0; i < d; ++i) nd[i] = phi.d[perm[i]];
     S->dims = nd;
     S->chi = phi.d[d];
     S->sigma_last = sig;
+    S->resplit_last = rsv;
     TRG_HIP_CHECK(hipStreamSynchronize(S->st));
     for (auto &t : T.c.timed) {
         float ms = 0.0f;
@@ -921,6 +1103,7 @@ void trg_default_options(trg_options *o) {
     o->bond_svd = TRG_SVD_SKETCH;
     o->max_sweeps = 300;
     o->tau_deg = trg::TAU_DEG_DEFAULT;
+    o->r_bond = 1;
 }
 
 int trg_create(const trg_options *opt, trg_state **out) {
@@ -931,6 +1114,8 @@ int trg_create(const trg_options *opt, trg_state **out) {
         (opt->precision < 0 || opt->precision > 3) || (opt->bond_svd != 0 && opt->bond_svd != 1))
         return TRG_E_INVALID;
     if (!(opt->tau_deg >= 0.0 && opt->tau_deg < 1.0)) return TRG_E_INVALID;
+    if (opt->r_bond < 1 || opt->sketch_mult < opt->r_bond) return TRG_E_INVALID;
+    if (opt->tangents < 0 || opt->tangents > (TRG_TAN_BETA | TRG_TAN_H)) return TRG_E_INVALID;
     trg_state *s = new (std::nothrow) trg_state();
     if (!s) return TRG_E_NOMEM;
     s->opt = *opt;
@@ -957,6 +1142,10 @@ int trg_destroy(trg_state *s) {
     else (void)hipDeviceSynchronize();
     if (s->phi) (void)hipFree(s->phi);
     if (s->psi) (void)hipFree(s->psi);
+    for (int t = 0; t < 2; ++t) {
+        if (s->dphi[t]) (void)hipFree(s->dphi[t]);
+        if (s->dpsi[t]) (void)hipFree(s->dpsi[t]);
+    }
     if (s->dscal) (void)hipFree(s->dscal);
     if (s->dint) (void)hipFree(s->dint);
     delete s;
@@ -970,9 +1159,39 @@ int tensor_init(trg_state *s, int model, double beta, double h, int D) {
     try {
         DevGuard g(s->opt.device);
         const int d = s->opt.dim;
-        size_t cap = 1;
-        for (int i = 0; i <= d; ++i) cap *= (size_t)std::max(D, 2);
+        // legs D^d, bond r_bond D (ILO keeps r_bond D bond values)
+        size_t cap = (size_t)std::max(s->opt.r_bond * D, 2);
+        for (int i = 0; i < d; ++i) cap *= (size_t)std::max(D, 2);
+        // the sketch's Philox counter packs the bond index in 8 bits; QRs are at most 512 wide
+        TRG_REQUIRE((long)s->opt.r_bond * D <= 256 && (long)s->opt.sketch_mult * D <= 512, TRG_E_UNSUPPORTED,
+                    "tensor_init: needs r_bond * D <= 256 and sketch_mult * D <= 512");
+        const int ntan = ((s->opt.tangents & TRG_TAN_BETA) ? 1 : 0) + ((s->opt.tangents & TRG_TAN_H) ? 1 : 0);
+        TRG_REQUIRE(!(s->opt.tangents & TRG_TAN_BETA) || beta > 0.0, TRG_E_INVALID,
+                    "tensor_init: the beta tangent needs beta > 0 (the CP factor sqrt(sinh beta) is not "
+                    "differentiable at 0)");
         s->init = false;   // set again only once the new state is complete
+        if (ntan > 0 && (cap > s->cap_tan || !s->dphi[ntan - 1])) {
+            if (s->st) (void)hipStreamSynchronize(s->st);
+            for (int t = 0; t < 2; ++t) {
+                if (s->dphi[t]) (void)hipFree(s->dphi[t]);
+                if (s->dpsi[t]) (void)hipFree(s->dpsi[t]);
+                s->dphi[t] = s->dpsi[t] = nullptr;
+            }
+            s->cap_tan = 0;
+            for (int t = 0; t < ntan; ++t) {
+                if (hipMalloc(&s->dphi[t], cap * sizeof(double)) != hipSuccess ||
+                    hipMalloc(&s->dpsi[t], cap * sizeof(double)) != hipSuccess) {
+                    (void)hipGetLastError();
+                    for (int u = 0; u < 2; ++u) {
+                        if (s->dphi[u]) (void)hipFree(s->dphi[u]);
+                        if (s->dpsi[u]) (void)hipFree(s->dpsi[u]);
+                        s->dphi[u] = s->dpsi[u] = nullptr;
+                    }
+                    throw Error(TRG_E_NOMEM, "tensor_init: cannot allocate the impurity tangents");
+                }
+            }
+            s->cap_tan = cap;
+        }
         if (cap > s->cap_state) {
             if (s->st) (void)hipStreamSynchronize(s->st);
             if (s->phi) (void)hipFree(s->phi);
@@ -1008,6 +1227,45 @@ int tensor_init(trg_state *s, int model, double beta, double h, int D) {
         hipStream_t st = s->st;
         TRG_HIP_CHECK(hipMemcpyAsync(s->phi, phi.data(), phi.size() * sizeof(double), hipMemcpyHostToDevice, st));
         TRG_HIP_CHECK(hipMemcpyAsync(s->psi, psi.data(), psi.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        // impurity tangents of the CP factors: d/dbeta differentiates every W (product
+        // rule over the legs), d/dh brings down s_a in Phi
+        std::vector<std::vector<double>> tphi, tpsi;
+        int kinds[2], nk = 0;
+        if (s->opt.tangents & TRG_TAN_BETA) kinds[nk++] = TRG_TAN_BETA;
+        if (s->opt.tangents & TRG_TAN_H) kinds[nk++] = TRG_TAN_H;
+        for (int t = 0; t < nk; ++t) {
+            std::vector<double> dp(F * 2, 0.0), dq(F * 2, 0.0);
+            for (int a = 0; a < 2; ++a) {
+                const double sa = a == 0 ? 1.0 : -1.0, fa = std::exp(h * sa);
+                for (int idx = 0; idx < F; ++idx) {
+                    double prod = 1.0, dprod = 0.0;
+                    for (int mu = 0; mu < d; ++mu) {
+                        const int i = (idx >> (d - 1 - mu)) & 1;
+                        if (kinds[t] == TRG_TAN_BETA) {
+                            const double dw = i == 0 ? std::sinh(beta) / (2.0 * cb)
+                                                     : (a == 0 ? 1.0 : -1.0) * std::cosh(beta) / (2.0 * sb);
+                            dprod = dprod * w[a][i] + prod * dw;
+                        }
+                        prod *= w[a][i];
+                    }
+                    if (kinds[t] == TRG_TAN_BETA) {
+                        dp[idx * 2 + a] = fa * dprod;
+                        dq[idx * 2 + a] = dprod;
+                    } else {
+                        dp[idx * 2 + a] = sa * fa * prod;
+                    }
+                }
+            }
+            tphi.push_back(dp);
+            tpsi.push_back(dq);
+            s->tan_kind[t] = kinds[t];
+        }
+        for (int t = 0; t < nk; ++t) {
+            TRG_HIP_CHECK(hipMemcpyAsync(s->dphi[t], tphi[t].data(), tphi[t].size() * sizeof(double),
+                                         hipMemcpyHostToDevice, st));
+            TRG_HIP_CHECK(hipMemcpyAsync(s->dpsi[t], tpsi[t].data(), tpsi[t].size() * sizeof(double),
+                                         hipMemcpyHostToDevice, st));
+        }
         double zero[2] = {0.0, 0.0};
         int izero[1] = {0};
         TRG_HIP_CHECK(hipMemcpyAsync(s->dscal, zero, sizeof(zero), hipMemcpyHostToDevice, st));
@@ -1019,8 +1277,10 @@ int tensor_init(trg_state *s, int model, double beta, double h, int D) {
         s->beta = beta;
         s->h = h;
         s->k = 0;
+        s->ntan = nk;
         s->init = true;
         s->sigma_last.clear();
+        s->resplit_last.clear();
     } catch (const Error &e) {
         return fail(s, e);
     } catch (const std::exception &e) {
@@ -1104,6 +1364,111 @@ int log_z_per_site(trg_state *s, double *out) {
     return TRG_OK;
 }
 
+int impurity_derivatives(trg_state *s, double *dbeta, double *dh) {
+    if (!s) return TRG_E_INVALID;
+    if (!s->init) return TRG_E_STATE;
+    if (s->ntan == 0) {
+        s->err = "impurity_derivatives: the state carries no tangents (trg_options.tangents)";
+        return TRG_E_STATE;
+    }
+    try {
+        DevGuard g(s->opt.device);
+        long n = (long)s->chi;
+        for (int v : s->dims) n *= v;
+        // Tr T and Tr dT = sum dPhi Psi + Phi dPsi, fixed-order partial sums
+        double *part = s->dscal + 1024;
+        double tr[3] = {0.0, 0.0, 0.0};
+        hipLaunchKernelGGL(trg::dot_partial_kernel, dim3(1024), dim3(256), 0, s->st, s->phi, s->psi, n, part);
+        hipLaunchKernelGGL(trg::sum_kernel, dim3(1), dim3(256), 0, s->st, part, 1024, s->dscal + 8);
+        for (int t = 0; t < s->ntan; ++t) {
+            hipLaunchKernelGGL(trg::dot_partial_kernel, dim3(512), dim3(256), 0, s->st, s->dphi[t], s->psi, n, part);
+            hipLaunchKernelGGL(trg::dot_partial_kernel, dim3(512), dim3(256), 0, s->st, s->phi, s->dpsi[t], n,
+                               part + 512);
+            hipLaunchKernelGGL(trg::sum_kernel, dim3(1), dim3(256), 0, s->st, part, 1024, s->dscal + 9 + t);
+        }
+        TRG_HIP_CHECK(hipGetLastError());
+        TRG_HIP_CHECK(hipMemcpyAsync(tr, s->dscal + 8, sizeof(tr), hipMemcpyDeviceToHost, s->st));
+        TRG_HIP_CHECK(hipStreamSynchronize(s->st));
+        if (!(tr[0] > 0.0) || !std::isfinite(tr[0])) throw Error(TRG_E_NUMERICAL, "final trace is not positive");
+        const double nan = std::nan("");
+        if (dbeta) *dbeta = nan;
+        if (dh) *dh = nan;
+        for (int t = 0; t < s->ntan; ++t) {
+            const double v = std::ldexp(tr[1 + t] / tr[0], -s->k);
+            if (s->tan_kind[t] == TRG_TAN_BETA && dbeta) *dbeta = v;
+            if (s->tan_kind[t] == TRG_TAN_H && dh) *dh = v;
+        }
+    } catch (const Error &e) {
+        return fail(s, e);
+    } catch (const std::exception &e) {
+        return fail_std(s, e);
+    }
+    return TRG_OK;
+}
+
+int gu_wen_x(trg_state *s, int axis, double *out) {
+    if (!s || !out) return TRG_E_INVALID;
+    if (!s->init) return TRG_E_STATE;
+    if (axis < 0 || axis >= (int)s->dims.size()) {
+        s->err = "gu_wen_x: axis out of range";
+        return TRG_E_INVALID;
+    }
+    trg::Arena::Mark mk = s->ar.mark();
+    try {
+        DevGuard g(s->opt.device);
+        trg::Ctx c;
+        c.st = s->st;
+        c.ar = &s->ar;
+        c.prec = trg::P_FP64;
+        trg::DT phi, psi;
+        phi.p = s->phi;
+        psi.p = s->psi;
+        phi.d = s->dims;
+        phi.d.push_back(s->chi);
+        psi.d = phi.d;
+        // A[k, l] = sum over the other legs and the bond of Phi[.., k, .., g] Psi[.., l, .., g]
+        std::string la, lb;
+        for (int i = 0; i < (int)s->dims.size(); ++i) {
+            la += i == axis ? 'k' : (char)('a' + i);
+            lb += i == axis ? 'l' : (char)('a' + i);
+        }
+        la += 'g';
+        lb += 'g';
+        trg::DT A = trg::contract(c, phi, la, psi, lb, "kl");
+        const int n = s->dims[axis];
+        hipLaunchKernelGGL(trg::gu_wen_kernel, dim3(1), dim3(256), 0, s->st, A.p, n, s->dscal + 4);
+        TRG_HIP_CHECK(hipGetLastError());
+        double tr[2];
+        TRG_HIP_CHECK(hipMemcpyAsync(tr, s->dscal + 4, sizeof(tr), hipMemcpyDeviceToHost, s->st));
+        TRG_HIP_CHECK(hipStreamSynchronize(s->st));
+        s->ar.release(mk);
+        if (!(tr[1] > 0.0) || !std::isfinite(tr[0]) || !std::isfinite(tr[1]))
+            throw Error(TRG_E_NUMERICAL, "gu_wen_x: Tr(A A) is not positive and finite");
+        *out = tr[0] * tr[0] / tr[1];
+    } catch (const Error &e) {
+        (void)hipStreamSynchronize(s->st);
+        s->ar.release(mk);
+        return fail(s, e);
+    } catch (const std::exception &e) {
+        (void)hipStreamSynchronize(s->st);
+        s->ar.release(mk);
+        return fail_std(s, e);
+    }
+    return TRG_OK;
+}
+
+int trg_release_workspace(trg_state *s) {
+    if (!s) return TRG_E_INVALID;
+    try {
+        DevGuard g(s->opt.device);
+        TRG_HIP_CHECK(hipStreamSynchronize(s->st));
+        s->ar.trim();
+    } catch (const Error &e) {
+        return fail(s, e);
+    }
+    return TRG_OK;
+}
+
 int trg_shape(trg_state *s, int *dims, int *chi, int *steps) {
     if (!s) return TRG_E_INVALID;
     if (!s->init) return TRG_E_STATE;
@@ -1120,6 +1485,7 @@ size_t trg_export_size(trg_state *s, int which) {
     for (int v : s->dims) n *= v;
     if (which == TRG_T_PHI || which == TRG_T_PSI) return n * sizeof(double);
     if (which == TRG_T_SIGMA) return s->sigma_last.size() * sizeof(double);
+    if (which == TRG_T_RESPLIT) return s->resplit_last.size() * sizeof(double);
     return 0;
 }
 
@@ -1132,6 +1498,10 @@ int trg_export(trg_state *s, int which, void *dst, size_t bytes) {
         DevGuard g(s->opt.device);
         if (which == TRG_T_SIGMA) {
             std::memcpy(dst, s->sigma_last.data(), need);
+            return TRG_OK;
+        }
+        if (which == TRG_T_RESPLIT) {
+            std::memcpy(dst, s->resplit_last.data(), need);
             return TRG_OK;
         }
         const double *src = which == TRG_T_PHI ? s->phi : s->psi;

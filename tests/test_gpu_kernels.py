@@ -57,6 +57,37 @@ def test_tsqr_rank_deficient():
     assert np.max(np.abs(q.T @ q - np.eye(12))) < 1e-12
 
 
+# wide QR (n > 64): blocked Householder over 64-column TSQR panels; ragged
+# last panels, square, and sketch-like heights
+@pytest.mark.parametrize("m,n", [(65, 65), (1000, 65), (777, 130), (5000, 96), (300, 200), (200000, 160),
+                                 (2000, 512)])
+def test_tsqr_wide(m, n):
+    _say("tsqr wide", m, n)
+    rng = np.random.default_rng(m + 3 * n)
+    a = rng.standard_normal((m, n)) * (10.0 ** -np.linspace(0, 8, n))[None, :]
+    q, r = trg.selftest_tsqr(a)
+    assert np.max(np.abs(q @ r - a)) < 1e-13 * np.max(np.abs(a))
+    assert np.max(np.abs(q.T @ q - np.eye(n))) < 1e-13
+    assert np.all(np.diagonal(r) >= 0)
+    assert np.all(np.tril(r, -1) == 0)
+    q2, r2 = np.linalg.qr(a)
+    sg = np.sign(np.diagonal(r2))
+    assert np.max(np.abs(r - r2 * sg[:, None])) < 1e-12 * np.max(np.abs(r))
+
+
+def test_tsqr_wide_rank_deficient():
+    # zero-padded and repeated columns, as a padded bond gives them
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal((4000, 140))
+    a[:, 70:95] = 0.0
+    a[:, 5] = 0.0
+    a[:, 120] = a[:, 3]
+    q, r = trg.selftest_tsqr(a)
+    assert np.max(np.abs(q @ r - a)) < 1e-12 * np.max(np.abs(a))
+    assert np.max(np.abs(q.T @ q - np.eye(140))) < 1e-13
+    assert np.all(np.diagonal(r) >= 0)
+
+
 @pytest.mark.parametrize("m,n", [(1, 1), (8, 8), (64, 64), (40, 17), (200, 120), (300, 300)])
 def test_jacobi_svd(m, n):
     _say("svd", m, n)
