@@ -96,6 +96,27 @@ void philox_sketch(double *out, uint64_t seed, int step, uint32_t instance,
                    const std::vector<int> &jdims, int chi, int m, int layout_jbm,
                    hipStream_t st);
 
+// ---- split-BF16 planes (gemm_bf16.hip) --------------------------------------------
+// An FP64 operand split into three BF16 planes x = x0 + x1 + x2, laid out
+// [plane][batch][row][Kp] (K contiguous, Kp a multiple of 32, zero padded).
+struct PlaneGemm {
+    const void *A, *B;          // planes of A (rows = M) and of B (rows = N)
+    long sAp, sAb, sBp, sBb;    // plane and batch strides (elements)
+    int M, N, Kp, batch;
+    int kslice, inner;          // K split in `inner` z-slices of kslice (multiples of 32)
+    double *C;
+    long sCr, sCn, sCb, sCi;    // C[batch][slice] strides, as GemmArgs
+    int cR2, cN2;
+    long sCr2, sCn2;
+    double alpha, beta;
+};
+size_t bf16_planes_elems(long rows, long Kp, int batch);
+// src[b][r][k] at src + b sB + r sR + k sK (rows x K, batch entries) -> planes in dst
+void split_bf16x3(const double *src, long sR, long sK, long sB, int rows, int K, int batch, int Kp, void *dst,
+                  hipStream_t st);
+// C = alpha sum_{i+j<=2} A_i B_j^T (+ beta C), FP32 MFMA accumulators flushed to FP64 per K tile
+void gemm_planes(const PlaneGemm &g, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
 // ---- factorizations -----------------------------------------------------------------
 // Thin QR of a (m x n, row-major, ld = n), n <= 64: q (m x n), r (n x n), diag r >= 0.
 // ws must hold tsqr_ws_doubles(m, n) doubles.

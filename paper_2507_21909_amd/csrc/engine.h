@@ -58,6 +58,8 @@ struct Ctx {
 
 // gemm() bracketed by HIP events on the context's stream when c.timing is set
 void timed_gemm(Ctx &c, const GemmArgs &g, Prec prec);
+// gemm_planes() likewise; flops = the contraction's algorithmic 2 M N K
+void timed_planes(Ctx &c, const PlaneGemm &g, double flops);
 
 DT talloc(Ctx &c, std::vector<int> dims);
 DT permuted(Ctx &c, const DT &a, const std::string &la, const std::string &lt);

@@ -232,6 +232,19 @@ void timed_gemm(Ctx &c, const GemmArgs &g, Prec prec) {
     c.timed.push_back(t);
 }
 
+void timed_planes(Ctx &c, const PlaneGemm &g, double flops) {
+    if (!c.timing) {
+        gemm_planes(g, c.st);
+        return;
+    }
+    TimedGemm t;
+    TRG_HIP_CHECK(hipEventCreate(&t.a));
+    TRG_HIP_CHECK(hipEventCreate(&t.b));
+    gemm_planes(g, c.st, t.a, t.b);
+    t.flops = flops;
+    c.timed.push_back(t);
+}
+
 void gemm(const GemmArgs &g, Prec prec, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     if (prec == P_FP64) gemm_f64(g, st, ev0, ev1);
     else gemm_mixed(g, (int)prec, st, ev0, ev1);

@@ -759,8 +759,82 @@ void triad_isos(Step &T, const DT *grams, int d1, int d2, int rcap, DT *U) {
 //       (rows (u, c) and columns (v, g) of the GEMM written interleaved)
 //   K2: out[x, k, l, c, g] = sum_{u, v} T23[u, v, k, l] Z[x, u, v, c, g]
 // u, v are the triad bonds (kA, kX), c the squeezed t3 bond, g the bond-swap bond.
+// round up to a multiple of 32 (the split planes' K padding)
+inline int pad32(long k) { return (int)((k + 31) / 32 * 32); }
+
+// planes for n elements of BF16 from the arena
+void *plane_alloc(Ctx &c, size_t n) { return c.ar->alloc(n * 2); }
+
+// makeMG / makeMH with split-BF16 contractions (BF16X6): EM, F and T23 are
+// split into BF16 planes once, Z once per slab group; K1 and K2 as gemm_planes
+DT coarse_half_planes(Step &T, const DT &em, const DT &fp, const DT &t23) {
+    Ctx &c = T.c;
+    const int X = em.d[0], U = em.d[1], C = em.d[2], Aa = em.d[3], Ss = em.d[4];
+    const int V = fp.d[2], G = fp.d[3];
+    const int Kk = t23.d[2], Ll = t23.d[3];
+    TRG_REQUIRE(fp.d[0] == Aa && fp.d[1] == Ss && t23.d[0] == U && t23.d[1] == V, -1, "coarse_half: shapes");
+    DT out = talloc(c, {X, Kk, Ll, C, G});
+    const long M1 = (long)U * C, N1 = (long)V * G, K1 = (long)Aa * Ss;
+    const long M2 = (long)Kk * Ll, N2 = (long)C * G, K2 = (long)U * V;
+    const int K1p = pad32(K1), K2p = pad32(K2);
+    Arena::Mark mk = c.ar->mark();
+    void *emp = plane_alloc(c, bf16_planes_elems(M1, K1p, X));
+    void *fpp = plane_alloc(c, bf16_planes_elems(N1, K1p, 1));
+    void *tpp = plane_alloc(c, bf16_planes_elems(M2, K2p, 1));
+    split_bf16x3(em.p, K1, 1, M1 * K1, (int)M1, (int)K1, X, K1p, emp, c.st);   // EM: rows (kA, k3), k (alpha, s)
+    split_bf16x3(fp.p, 1, N1, 0, (int)N1, (int)K1, 1, K1p, fpp, c.st);       // F: rows (kX, g), k (alpha, s)
+    split_bf16x3(t23.p, 1, M2, 0, (int)M2, (int)K2, 1, K2p, tpp, c.st);      // T23: rows (k1, k2), k (kA, kX)
+    const long zslab = (long)U * C * V * G;
+    int xs = (int)std::max(1L, std::min<long>(X, (long)(134217728L / std::max(1L, zslab))));
+    DT z = talloc(c, {xs, U, V, C, G});
+    void *zp = plane_alloc(c, bf16_planes_elems(N2, K2p, xs));
+    // K2 has few output tiles: split K so the launch fills the CUs
+    const long tiles2 = ((M2 + 127) / 128) * ((N2 + 127) / 128) * xs;
+    int inner = 1;
+    while (inner < 16 && tiles2 * inner < 1024 && K2p / (2 * inner) >= 2048) inner *= 2;
+    const int kslice = pad32((K2p + inner - 1) / inner);
+    inner = (K2p + kslice - 1) / kslice;
+    const long mn = M2 * N2;
+    double *kws = inner > 1 ? c.ar->dalloc((size_t)xs * inner * mn) : nullptr;
+    for (int x0 = 0; x0 < X; x0 += xs) {
+        const int nx = std::min(xs, X - x0);
+        PlaneGemm g{};
+        g.A = static_cast<const char *>(emp) + 2 * (size_t)x0 * M1 * K1p;
+        g.sAp = (long)X * M1 * K1p; g.sAb = M1 * K1p;
+        g.B = fpp; g.sBp = N1 * K1p; g.sBb = 0;
+        g.M = (int)M1; g.N = (int)N1; g.Kp = K1p; g.batch = nx;
+        g.kslice = K1p; g.inner = 1;
+        // rows (kA, k3) and columns (kX, g) land in Z's [x, kA, kX, k3, g] layout
+        g.C = z.p; g.sCb = zslab;
+        g.cR2 = C; g.sCr = (long)V * C * G; g.sCr2 = G;
+        g.cN2 = G; g.sCn = (long)C * G; g.sCn2 = 1;
+        g.alpha = 1.0; g.beta = 0.0;
+        timed_planes(c, g, 2.0 * M1 * N1 * K1 * nx);
+        // Z as K2's B operand: rows (k3, g), k (kA, kX)
+        split_bf16x3(z.p, 1, N2, zslab, (int)N2, (int)K2, nx, K2p, zp, c.st);
+        PlaneGemm h{};
+        h.A = tpp; h.sAp = M2 * K2p; h.sAb = 0;
+        h.B = zp; h.sBp = (long)nx * N2 * K2p; h.sBb = N2 * K2p;
+        h.M = (int)M2; h.N = (int)N2; h.Kp = K2p; h.batch = nx;
+        h.kslice = kslice; h.inner = inner;
+        h.alpha = 1.0; h.beta = 0.0;
+        if (inner > 1) {
+            h.C = kws; h.sCr = N2; h.sCn = 1; h.sCb = (long)inner * mn; h.sCi = mn;
+            timed_planes(c, h, 2.0 * M2 * N2 * K2 * nx);
+            for (int x = 0; x < nx; ++x)
+                sum_slices(kws + (long)x * inner * mn, inner, M2, N2, out.p + (long)(x0 + x) * mn, N2, 1, c.st);
+        } else {
+            h.C = out.p + (long)x0 * mn; h.sCr = N2; h.sCn = 1; h.sCb = mn;
+            timed_planes(c, h, 2.0 * M2 * N2 * K2 * nx);
+        }
+    }
+    c.ar->release(mk);
+    return out;
+}
+
 DT coarse_half(Step &T, const DT &em, const DT &fp, const DT &t23) {
     Ctx &c = T.c;
+    if (c.prec == P_BF16X6) return coarse_half_planes(T, em, fp, t23);
     const int X = em.d[0], U = em.d[1], C = em.d[2], Aa = em.d[3], Ss = em.d[4];
     const int V = fp.d[2], G = fp.d[3];
     const int Kk = t23.d[2], Ll = t23.d[3];
@@ -1677,8 +1751,32 @@ int trg_selftest_gemm(int precision, int ta, int tb, int M, int N, int K, int ba
         g.B = b; g.sBk = tb ? 1 : N; g.sBn = tb ? K : 1; g.sBb = (long)K * N;
         g.C = c; g.sCr = N; g.sCn = 1; g.sCb = (long)M * N;
         g.alpha = 1.0; g.beta = 0.0;
-        if (K == 0) trg::fill(c, nc, 0.0, nullptr);
-        else trg::gemm(g, (trg::Prec)precision, nullptr);
+        if (K == 0) {
+            trg::fill(c, nc, 0.0, nullptr);
+        } else if (precision == trg::P_BF16X6) {
+            // the coarse-graining path of BF16X6: both operands split into planes, then
+            // gemm_planes with K split in slices of at least 64
+            const int Kp = (K + 31) / 32 * 32;
+            void *ap = s.ar.alloc(trg::bf16_planes_elems(M, Kp, batch) * 2);
+            void *bp = s.ar.alloc(trg::bf16_planes_elems(N, Kp, batch) * 2);
+            trg::split_bf16x3(a, g.sAr, g.sAk, g.sAb, M, K, batch, Kp, ap, nullptr);
+            trg::split_bf16x3(b, g.sBn, g.sBk, g.sBb, N, K, batch, Kp, bp, nullptr);
+            trg::PlaneGemm h{};
+            h.A = ap; h.sAp = (long)batch * M * Kp; h.sAb = (long)M * Kp;
+            h.B = bp; h.sBp = (long)batch * N * Kp; h.sBb = (long)N * Kp;
+            h.M = M; h.N = N; h.Kp = Kp; h.batch = batch;
+            h.inner = Kp >= 128 ? 2 : 1;
+            h.kslice = (Kp / h.inner + 31) / 32 * 32;
+            h.inner = (Kp + h.kslice - 1) / h.kslice;
+            double *w = s.ar.dalloc(nc * h.inner);
+            h.C = w; h.sCr = N; h.sCn = 1; h.sCb = (long)h.inner * M * N; h.sCi = (long)M * N;
+            h.alpha = 1.0; h.beta = 0.0;
+            trg::gemm_planes(h, nullptr);
+            for (int bt = 0; bt < batch; ++bt)
+                trg::sum_slices(w + (long)bt * h.inner * M * N, h.inner, M, N, c + (long)bt * M * N, N, 1, nullptr);
+        } else {
+            trg::gemm(g, (trg::Prec)precision, nullptr);
+        }
         s.down(C, c, nc);
     } catch (const Error &e) {
         g_err = e.what();
