@@ -13,8 +13,9 @@
 //
 // Tiling: a 512-thread workgroup owns a 128 x 128 tile of C; its eight
 // wavefronts (4 x 2) own 32 x 64 strips (one row block and two column blocks
-// of 32 x 32).  A K tile of the three planes of both operands (48 KB) is
-// staged through LDS, the next one prefetched into registers meanwhile.
+// of 32 x 32).  K tiles of the three planes of both operands (48 KB each) are
+// double-buffered in LDS, one barrier per tile, the tile after next
+// prefetched into registers meanwhile.
 // Workgroups are mapped to tiles XCD by XCD, in groups of 8 tile rows, so a
 // group's A panels and the current B panel stay in one XCD's L2.
 #include <hip/hip_ext.h>
@@ -120,8 +121,9 @@ __global__ __launch_bounds__(PNT) void gemm_planes_kernel(PlaneGemm g) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
 
-    __shared__ __bf16 As[3][PT][PK + PPAD];
-    __shared__ __bf16 Bs[3][PT][PK + PPAD];
+    // two K tiles of both operands' planes (double-buffered, 120 KB)
+    __shared__ __bf16 As[2][3][PT][PK + PPAD];
+    __shared__ __bf16 Bs[2][3][PT][PK + PPAD];
 
     // loader: thread t moves the 16-byte chunk (row t / 4, k chunk t % 4) of each plane
     const int lr = t >> 2, lk = (t & 3) * 8;
@@ -136,11 +138,11 @@ __global__ __launch_bounds__(PNT) void gemm_planes_kernel(PlaneGemm g) {
             rb[p] = b_in ? *reinterpret_cast<const uint4 *>(gb + p * g.sBp + k0) : make_uint4(0, 0, 0, 0);
         }
     };
-    auto store = [&]() {
+    auto store = [&](int buf) {
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-            *reinterpret_cast<uint4 *>(&As[p][lr][lk]) = ra[p];
-            *reinterpret_cast<uint4 *>(&Bs[p][lr][lk]) = rb[p];
+            *reinterpret_cast<uint4 *>(&As[buf][p][lr][lk]) = ra[p];
+            *reinterpret_cast<uint4 *>(&Bs[buf][p][lr][lk]) = rb[p];
         }
     };
 
@@ -157,22 +159,27 @@ __global__ __launch_bounds__(PNT) void gemm_planes_kernel(PlaneGemm g) {
     const int arow = wr * 32 + (lane & 31), kl = (lane >> 5) * 8;
     const int bcol = wc * 64 + (lane & 31);
 
+    // tile i is multiplied from buffer i % 2 while tile i + 1 goes from the
+    // registers into the other buffer and tile i + 2 is fetched: one barrier a tile
     if (kbeg < kend) {
         load(kbeg);
-        store();
+        store(0);
+        if (kbeg + PK < kend) load(kbeg + PK);
     }
     __syncthreads();
+    int buf = 0;
     for (int k0 = kbeg; k0 < kend; k0 += PK) {
-        const bool more = k0 + PK < kend;
-        if (more) load(k0 + PK);
+        // raised priority while this wave's MFMAs issue; the other waves' LDS
+        // traffic fills in around them
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int ks = 0; ks < PK; ks += 16) {
             bf8 a[3], b[2][3];
 #pragma unroll
             for (int p = 0; p < 3; ++p) {
-                a[p] = *reinterpret_cast<const bf8 *>(&As[p][arow][ks + kl]);
-                b[0][p] = *reinterpret_cast<const bf8 *>(&Bs[p][bcol][ks + kl]);
-                b[1][p] = *reinterpret_cast<const bf8 *>(&Bs[p][bcol + 32][ks + kl]);
+                a[p] = *reinterpret_cast<const bf8 *>(&As[buf][p][arow][ks + kl]);
+                b[0][p] = *reinterpret_cast<const bf8 *>(&Bs[buf][p][bcol][ks + kl]);
+                b[1][p] = *reinterpret_cast<const bf8 *>(&Bs[buf][p][bcol + 32][ks + kl]);
             }
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -185,6 +192,7 @@ __global__ __launch_bounds__(PNT) void gemm_planes_kernel(PlaneGemm g) {
                 acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[j][0], acc[j], 0, 0, 0);
             }
         }
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
 #pragma unroll
@@ -193,11 +201,12 @@ __global__ __launch_bounds__(PNT) void gemm_planes_kernel(PlaneGemm g) {
                 acc[j][e] = 0.0f;
             }
         }
-        __syncthreads();
-        if (more) {
-            store();
-            __syncthreads();
+        if (k0 + PK < kend) {
+            store(buf ^ 1);
+            if (k0 + 2 * PK < kend) load(k0 + 2 * PK);
         }
+        __syncthreads();
+        buf ^= 1;
     }
     // 32 x 32 block output: element e of lane l is row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
 #pragma unroll
