@@ -18,7 +18,8 @@
  *     stream when NULL).  A step reads the convergence flags of its
  *     eigensolvers and SVDs and its numerical status back on the host, so it
  *     returns with the stream synchronised; log_z_per_site and the
- *     export/inspection calls synchronise it too.  The caller keeps a stream
+ *     export/inspection calls synchronise it too.  The asynchronous form of
+ *     a step is a captured one (trg_graph_launch).  The caller keeps a stream
  *     it passed alive until trg_destroy.
  *   - A step that fails leaves the state as it was before the step (tensors,
  *     step count and log-norm accumulator), so log_z_per_site still gives
@@ -45,6 +46,7 @@ extern "C" {
 #define TRG_E_NUMERICAL -4   /* NaN/Inf, non-positive norm, Jacobi not converged in max_sweeps       */
 #define TRG_E_HIP       -5   /* HIP runtime error (message kept in trg_last_error)                    */
 #define TRG_E_UNSUPPORTED -6 /* a shape outside the kernels' documented limits                       */
+#define TRG_E_MULTIPLET -7   /* a truncation cut falls inside a multiplet of more than 16 values      */
 
 /* ---- options ---------------------------------------------------------- */
 #define TRG_MODEL_ISING 0
@@ -111,7 +113,9 @@ int tensor_init(trg_state *s, int model, double beta, double h, int D);
  * atrg_step -- one ATRG coarse-graining step along `axis` (0..dim-1):
  * exact re-split of T (Fig. 5f), bond swap (eq. of the bond swap, App. A),
  * squeezers from the canonical Gamma^ATRG and makeG / makeH (Sec. II A).
- * Halves the lattice along `axis`.  Asynchronous.
+ * Halves the lattice along `axis`.  Returns with the stream synchronised
+ * (it reads its status back); trg_graph_launch replays a captured step
+ * asynchronously.
  */
 int atrg_step(trg_state *s, int axis);
 
@@ -120,7 +124,7 @@ int atrg_step(trg_state *s, int axis);
  * re-split, bond swap, triad isometries from the truncated HOSVD of
  * Gamma^ATRG (eq. HOSVD), triad tensors E..L, squeezers from Gamma^Triad
  * with the Gram matrices O and P (Sec. II D), makeMG / makeMH (Sec. II B).
- * Asynchronous.
+ * Synchronises as atrg_step does.
  */
 int triad_atrg_step(trg_state *s, int axis);
 
@@ -168,6 +172,42 @@ int impurity_derivatives(trg_state *s, double *dbeta, double *dh);
  * again).  The state tensors stay.  Synchronises the state's stream first.
  */
 int trg_release_workspace(trg_state *s);
+
+/*
+ * Captured steps (HIP graphs) -- the RG loop without host round trips.
+ *
+ * trg_graph_capture records one step of `method` (TRG_METHOD_ATRG or
+ * TRG_METHOD_TRIAD) along `axis` into a HIP graph, at the state's current
+ * shapes, without running it; *out receives the graph.  The state must have
+ * run at least one eager step of the same method at these shapes since its
+ * last tensor_init: that step sized the workspace (nothing may be allocated
+ * while recording) and logged how many sweeps each Jacobi solve needed.
+ * Otherwise TRG_E_STATE, and the state is unchanged.  The recorded step
+ * reads nothing back: the panel Jacobi solves run at most 1.5 times the most
+ * sweeps logged for them plus 4, stopping early on device flags, and
+ * numerical failures set the state's device status flag.  Neither an
+ * n > 1024 squeezer Gram nor the eigensolver fallback can be recorded
+ * (TRG_E_UNSUPPORTED).
+ *
+ * trg_graph_launch enqueues the recorded step on the state's stream and
+ * returns without waiting; the state then holds the next step's tensors,
+ * step count, spectra and log-norm, bit for bit those of the eager step
+ * (same kernels in the same order).  A failure inside a launched step is
+ * reported by the next call that reads the status (log_z_per_site) as
+ * TRG_E_NUMERICAL or TRG_E_MULTIPLET, with no rollback.  TRG_E_STATE if the
+ * state's shapes differ from those at capture, or if tensor_init or
+ * trg_release_workspace ran on the state since the capture.
+ *
+ * trg_graph_destroy frees a graph (NULL: no-op); destroy graphs before their
+ * state.  One graph per (method, axis) covers a steady RG loop: the shapes
+ * stop changing once the bond dimension reaches its cap.
+ */
+#define TRG_METHOD_ATRG  0
+#define TRG_METHOD_TRIAD 1
+typedef struct trg_graph trg_graph;
+int trg_graph_capture(trg_state *s, int method, int axis, trg_graph **out);
+int trg_graph_launch(trg_graph *g);
+int trg_graph_destroy(trg_graph *g);
 
 /* ---- many instances ------------------------------------------------------ */
 

@@ -16,6 +16,7 @@ SVD_SKETCH, SVD_EXACT = 0, 1
 TAN_BETA, TAN_H = 1, 2
 MODEL_ISING = 0
 T_PHI, T_PSI, T_SIGMA, T_RESPLIT = 0, 1, 2, 3
+METHOD_ATRG, METHOD_TRIAD = 0, 1
 
 
 class Options(ctypes.Structure):
@@ -100,6 +101,13 @@ def load_library(path=None):
     lib.trg_qr.restype = ctypes.c_int
     lib.trg_qr_noalloc.argtypes = lib.trg_qr.argtypes
     lib.trg_qr_noalloc.restype = ctypes.c_int
+    lib.trg_release_workspace.argtypes = [st]
+    lib.trg_release_workspace.restype = ctypes.c_int
+    lib.trg_graph_capture.argtypes = [st, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+    lib.trg_graph_launch.argtypes = [ctypes.c_void_p]
+    lib.trg_graph_destroy.argtypes = [ctypes.c_void_p]
+    for f in ("trg_graph_capture", "trg_graph_launch", "trg_graph_destroy"):
+        getattr(lib, f).restype = ctypes.c_int
     for f in ("trg_batch_create", "trg_batch_run", "trg_batch_log_z", "trg_batch_size", "trg_batch_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     for f in ("trg_create", "trg_destroy", "tensor_init", "atrg_step", "triad_atrg_step", "log_z_per_site", "gu_wen_x",
@@ -200,10 +208,42 @@ class Solver:
     def set_timing(self, on=True):
         _check(self._lib.trg_set_timing(self._s, 1 if on else 0), self._s)
 
+    def release_workspace(self):
+        """Free the step workspace (trg_release_workspace); recorded graphs of this state retire."""
+        _check(self._lib.trg_release_workspace(self._s), self._s)
+
+    def capture(self, axis, method=METHOD_TRIAD):
+        """Record one step along ``axis`` at the current shapes as a HIP graph (trg_graph_capture)."""
+        g = ctypes.c_void_p()
+        _check(self._lib.trg_graph_capture(self._s, method, axis, ctypes.byref(g)), self._s)
+        return Graph(self, g)
+
     def kernel_time(self):
         ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
         _check(self._lib.trg_kernel_time(self._s, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n)), self._s)
         return ms.value, fl.value, n.value
+
+
+class Graph:
+    """A recorded RG step (trg_graph); ``launch()`` replays it on the solver's stream."""
+
+    def __init__(self, solver, handle):
+        self._solver = solver   # destroyed before the solver: keep it alive
+        self._g = handle
+
+    def launch(self):
+        _check(self._solver._lib.trg_graph_launch(self._g), self._solver._s)
+
+    def close(self):
+        if self._g:
+            self._solver._lib.trg_graph_destroy(self._g)
+            self._g = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

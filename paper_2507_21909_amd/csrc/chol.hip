@@ -206,6 +206,14 @@ __global__ void zero_upper_kernel(double *K, int n, int count, const int *rk) {
         if (j > i || (rk && j >= rk[mat])) K[e] = 0.0;
     }
 }
+
+// device-side verdict of the pivoted factorisation: a non-finite pivot in any
+// matrix sets *dstatus = 4
+__global__ void pchol_check_kernel(const int *status, int count, int *dstatus) {
+    if (threadIdx.x) return;
+    for (int i = 0; i < count; ++i)
+        if (status[i]) *dstatus = 4;
+}
 }  // namespace
 
 size_t chol_ws_doubles(int count, int n) { return (size_t)count * (CB * CB + (size_t)n * CB) + 64; }
@@ -214,7 +222,8 @@ size_t chol_ws_doubles(int count, int n) { return (size_t)count * (CB * CB + (si
 size_t pchol_iws_ints(int count, int n) { return (size_t)count * (n + 4) + 16; }
 
 bool pivoted_cholesky_batched(double *K, int count, int n, double *X, int *iws, hipStream_t st, double tol,
-                              int *rank) {
+                              int *rank, int *dstatus) {
+    TRG_REQUIRE(!(dstatus && rank), -1, "pivoted Cholesky: no host rank with a device status");
     if (count == 0 || n == 0) return true;
     TRG_REQUIRE(n <= 1024, -6, "pivoted Cholesky: n > 1024");
     TRG_REQUIRE(tol >= 0.0 && tol < 1.0, -1, "pivoted Cholesky: tolerance outside [0, 1)");
@@ -223,7 +232,7 @@ bool pivoted_cholesky_batched(double *K, int count, int n, double *X, int *iws, 
     int *status = iws + 2 * count, *rk = status + count, *perm = rk + count;
     const unsigned gb = (unsigned)std::min<size_t>(((size_t)count * n + 255) / 256, 65536);
     hipLaunchKernelGGL(perm_init_kernel, dim3(gb), dim3(256), 0, st, perm, rk, status, n, count);
-    TRG_HIP_CHECK(hipMemsetAsync(X, 0, sizeof(double) * count * n * n, st));
+    fill(X, (size_t)count * n * n, 0.0, st);
     for (int j0 = 0; j0 < n; j0 += PCW) {
         const int nb = std::min(PCW, n - j0);
         hipLaunchKernelGGL(pchol_panel_kernel, dim3(count), dim3(PCT), 0, st, K, n, j0, nb, perm, status, rk, dtop,
@@ -238,6 +247,11 @@ bool pivoted_cholesky_batched(double *K, int count, int n, double *X, int *iws, 
         h.C = K; h.sCr = n; h.sCn = 1; h.sCb = (long)n * n;
         h.alpha = -1.0; h.beta = 1.0;
         gemm(h, P_FP64, st);
+    }
+    if (dstatus) {
+        hipLaunchKernelGGL(pchol_check_kernel, dim3(1), dim3(64), 0, st, status, count, dstatus);
+        TRG_HIP_CHECK(hipGetLastError());
+        return true;
     }
     std::vector<int> fl(2 * count);   // status, then rk
     TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), status, sizeof(int) * 2 * count, hipMemcpyDeviceToHost, st));

@@ -92,9 +92,10 @@ void canonical_rotation(const double *q, long rows, int cols, long ld, const std
 // a[:, j] *= sg[j]
 void scale_cols(double *a, long rows, int cols, long ld, const double *sg, hipStream_t st);
 
+// step_dev (optional): the step index is read there, on the device, instead of `step`
 void philox_sketch(double *out, uint64_t seed, int step, uint32_t instance,
                    const std::vector<int> &jdims, int chi, int m, int layout_jbm,
-                   hipStream_t st);
+                   hipStream_t st, const int *step_dev = nullptr);
 
 // ---- split-BF16 planes (gemm_bf16.hip) --------------------------------------------
 // An FP64 operand split into three BF16 planes x = x0 + x1 + x2, laid out
@@ -132,8 +133,19 @@ struct JacobiBatch {
     double *vt;   // count * n * n
     long strideU, strideV;
 };
-// work: count * (n + 1) doubles (per-matrix scale, then column norms).
-int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *work, hipStream_t st);
+// Device-driven convergence (graph capture): the solver enqueues `sweeps`
+// sweeps and reads nothing back; once a sweep makes no rotation the remaining
+// launches return at once.  Non-finite pairs, or rotations still made in the
+// last sweep, set *status = code.
+struct DevLoop {
+    int sweeps;
+    int *status;
+    int code;
+};
+// work: count * (n + 1) doubles (per-matrix scale, then column norms); flags_dev:
+// 2 * count + 1 ints.  With dl the return value is -1 (sweeps not known on the host).
+int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *work, hipStream_t st,
+               const DevLoop *dl = nullptr);
 // After jacobi_svd: s (count x n) descending singular values, U columns normalized
 // and sorted into u_sorted (row-major m x n, may be null), V sorted into v_sorted
 // (row-major n x n).
@@ -156,9 +168,11 @@ bool cholesky_batched(double *K, int count, int n, double *ws, int *status_dev, 
 // tol > 0: a matrix's factorisation stops at the first pivot at or below tol
 // times its first pivot and the remaining columns of X are zero; false only for
 // a non-finite pivot.  rank (host, count ints, optional): columns formed.
+// dstatus (device int, optional): nothing is read back; a failed pivot sets
+// *dstatus = 4 and the call returns true.
 size_t pchol_iws_ints(int count, int n);
 bool pivoted_cholesky_batched(double *K, int count, int n, double *X, int *iws, hipStream_t st, double tol = 0.0,
-                              int *rank = nullptr);
+                              int *rank = nullptr, int *dstatus = nullptr);
 void jacobi_finish(const JacobiBatch &jb, double *s, double *u_sorted, double *v_sorted,
                    double *work, hipStream_t st);
 

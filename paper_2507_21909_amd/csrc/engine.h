@@ -1,6 +1,8 @@
 // Host engine of the RG step: device arena, tensor contraction over labelled
 // legs, and the state of one solve.
 #pragma once
+#include <array>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -24,11 +26,14 @@ class Arena {
     void trim();
     size_t held() const { return total_; }
     void set_cap(size_t c) { cap_ = c; }
+    // frozen: an allocation that needs a new chunk throws instead (graph capture)
+    void freeze(bool f) { frozen_ = f; }
 
   private:
     struct Chunk { char *base; size_t cap, used; };
     std::vector<Chunk> chunks_;
     size_t cur_ = 0, total_ = 0, cap_ = 0;
+    bool frozen_ = false;
 };
 
 // Device tensor: row-major, leftmost leg slowest.
@@ -54,6 +59,13 @@ struct Ctx {
     // HIP events around selected GEMM launches (the coarse-graining GEMMs)
     bool timing = false;
     std::vector<TimedGemm> timed;
+    // graph capture: nothing is read back to the host; iterative solves stop on
+    // device flags and report failures in *dstatus
+    bool capture = false;
+    int *dstatus = nullptr;
+    // sweeps eager solves took, keyed by (call order, count, m, n); solve_idx counts calls
+    std::map<std::array<int, 4>, int> *sweep_log = nullptr;
+    int solve_idx = 0;
 };
 
 // gemm() bracketed by HIP events on the context's stream when c.timing is set

@@ -30,6 +30,8 @@ void *Arena::alloc(size_t bytes) {
         ++cur_;
         if (cur_ < chunks_.size()) chunks_[cur_].used = 0;
     }
+    TRG_REQUIRE(!frozen_, -2,
+                "graph capture: the workspace would grow (run one eager step of this method at these shapes first)");
     size_t want = std::max(bytes, size_t(256) << 20);
     if (cap_ && total_ + want > cap_) {
         want = bytes;

@@ -12,6 +12,7 @@
 // two columns of U and of V.  Large n: one launch per round, all matrices of a
 // batch together.  Small n: one workgroup per matrix loops over every round
 // and sweep in a single launch.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -103,6 +104,7 @@ __device__ int rotate_pair(double *u, double *v, int m, int n, int mm, int r, in
 
 // flags[mat]: rotations of this sweep; flags[count + mat]: non-finite pairs seen
 __global__ __launch_bounds__(NT) void round_kernel(JacobiBatch jb, int r, double tol, int *flags) {
+    if (flags[2 * jb.count]) return;   // solve already converged (device-driven sweeps)
     const int mat = blockIdx.y;
     const int k = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
     const int mm = jb.n + (jb.n & 1);
@@ -210,6 +212,7 @@ __device__ inline void shift_cross(double (&u)[PW][ROWS], double (&vrow)[PW]) {
 template <int ROWS, bool WV>
 __global__ __launch_bounds__(NT) void panel_kernel(JacobiBatch jb, int nb, int r, double tol, int max_inner,
                                                    int cross, int *flags) {
+    if (flags[2 * jb.count]) return;   // solve already converged (device-driven sweeps)
     const int k = blockIdx.x, mat = blockIdx.y, t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int I = player_at(nb, k, r), J = player_at(nb, nb - 1 - k, r);
     double *U = jb.ut + (long)mat * jb.strideU;
@@ -466,6 +469,38 @@ __global__ void sort_gather_kernel(JacobiBatch jb, const double *scale, const do
         for (int i = threadIdx.x; i < jb.n; i += blockDim.x) vo[(long)i * jb.n + rk] = v[i];
     }
 }
+
+// flags layout: [0, count) rotations of the sweep, [count, 2 count) non-finite
+// pairs seen, [2 count] done (no launch of the solve does anything once set)
+__global__ void flags_init_kernel(int *flags, int count) {
+    for (int i = threadIdx.x; i <= 2 * count; i += blockDim.x) flags[i] = 0;
+}
+
+__global__ void sweep_begin_kernel(int *flags, int count) {
+    if (flags[2 * count]) return;
+    for (int i = threadIdx.x; i < 2 * count; i += blockDim.x) flags[i] = 0;
+}
+
+// end of a device-driven sweep: the solve is done once no matrix rotated; a
+// non-finite pair, or rotations left after the last allowed sweep, set
+// *status = code
+__global__ void sweep_end_kernel(int *flags, int count, int last, int *status, int code) {
+    if (threadIdx.x || flags[2 * count]) return;
+    int any = 0, bad = 0;
+    for (int i = 0; i < count; ++i) {
+        any |= flags[i] != 0;
+        bad |= flags[count + i] != 0;
+    }
+    if (bad || (any && last)) *status = code;
+    if (bad || !any || last) flags[2 * count] = 1;
+}
+
+// the one-launch solver's verdict, device side: flags[i] < 0 is no convergence
+__global__ void full_check_kernel(const int *flags, int count, int *status, int code) {
+    if (threadIdx.x) return;
+    for (int i = 0; i < count; ++i)
+        if (flags[i] < 0 || flags[count + i] != 0) *status = code;
+}
 }  // namespace
 
 namespace {
@@ -495,8 +530,9 @@ bool trace_on() {
 }
 }  // namespace
 
-// flags_dev: 2 * count ints of device scratch
-int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *work, hipStream_t st) {
+// flags_dev: 2 * count + 1 ints of device scratch
+int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *work, hipStream_t st,
+               const DevLoop *dl) {
     if (jb.count == 0 || jb.n == 0) return 0;
     const double tol = sqrt((double)jb.m) * 2.220446049250313e-16;
     hipLaunchKernelGGL(scale_kernel, dim3(jb.count), dim3(NT), 0, st, jb, work);
@@ -508,6 +544,11 @@ int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *wo
     if (jb.n <= 96) {
         hipLaunchKernelGGL(full_kernel, dim3(jb.count), dim3(NT), 0, st, jb, max_sweeps, tol, flags_dev);
         TRG_HIP_CHECK(hipGetLastError());
+        if (dl) {
+            hipLaunchKernelGGL(full_check_kernel, dim3(1), dim3(64), 0, st, flags_dev, jb.count, dl->status, dl->code);
+            TRG_HIP_CHECK(hipGetLastError());
+            return -1;
+        }
         TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), flags_dev, sizeof(int) * 2 * jb.count, hipMemcpyDeviceToHost, st));
         TRG_HIP_CHECK(hipStreamSynchronize(st));
         int worst = 0;
@@ -522,8 +563,10 @@ int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *wo
     }
     const bool panel = jb.m <= 4 * NT;
     const int nbk = ((jb.n + PW - 1) / PW) * PW / 8;   // blocks of 8 columns (even)
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        TRG_HIP_CHECK(hipMemsetAsync(flags_dev, 0, sizeof(int) * 2 * jb.count, st));
+    hipLaunchKernelGGL(flags_init_kernel, dim3(1), dim3(256), 0, st, flags_dev, jb.count);
+    const int nsweeps = dl ? std::min(dl->sweeps, max_sweeps) : max_sweeps;
+    for (int sweep = 0; sweep < nsweeps; ++sweep) {
+        hipLaunchKernelGGL(sweep_begin_kernel, dim3(1), dim3(256), 0, st, flags_dev, jb.count);
         if (panel) {
             dim3 grid(nbk / 2, jb.count);
             // the first launch of a sweep also takes the pairs inside every block
@@ -541,6 +584,12 @@ int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *wo
                 hipLaunchKernelGGL(round_kernel, grid, dim3(NT), 0, st, jb, r, tol, flags_dev);
         }
         TRG_HIP_CHECK(hipGetLastError());
+        if (dl) {
+            hipLaunchKernelGGL(sweep_end_kernel, dim3(1), dim3(64), 0, st, flags_dev, jb.count,
+                               sweep + 1 == nsweeps ? 1 : 0, dl->status, dl->code);
+            TRG_HIP_CHECK(hipGetLastError());
+            continue;
+        }
         TRG_HIP_CHECK(hipMemcpyAsync(fl.data(), flags_dev, sizeof(int) * 2 * jb.count, hipMemcpyDeviceToHost, st));
         TRG_HIP_CHECK(hipStreamSynchronize(st));
         bool any = false, bad = false;
@@ -555,6 +604,7 @@ int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *wo
         if (!any) return sweep;
         if (sweep + 1 == max_sweeps) not_converged(jb, fl, false);
     }
+    if (dl) return -1;
     throw Error(-4, "Jacobi SVD did not converge");
 }
 

@@ -161,6 +161,7 @@ __device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
 
 struct SketchArgs {
     uint32_t k0, k1, instance, step;
+    const int *stepp;   // step index read on the device (replayed graphs), else step
     int j1, j2, j3, chi, m, layout_jbm;
     long total;
 };
@@ -168,6 +169,7 @@ struct SketchArgs {
 // Omega entry for multi-index (beta, j1, j2, j3, m): standard normal from the
 // first two Philox words (Box-Muller, cosine branch).
 __global__ void sketch_kernel(double *out, SketchArgs a) {
+    const uint32_t step = a.stepp ? (uint32_t)*a.stepp : a.step;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < a.total; i += (long)gridDim.x * blockDim.x) {
         long rem = i;
         int mm = (int)(rem % a.m); rem /= a.m;
@@ -184,7 +186,7 @@ __global__ void sketch_kernel(double *out, SketchArgs a) {
             b = (int)rem;
         }
         uint32_t c[4] = {(uint32_t)x1 | ((uint32_t)x2 << 8) | ((uint32_t)x3 << 16) | ((uint32_t)b << 24),
-                         (uint32_t)mm | ((a.step & 0xFFFFu) << 16), a.instance, 0x4F4D4547u};
+                         (uint32_t)mm | ((step & 0xFFFFu) << 16), a.instance, 0x4F4D4547u};
         philox(c, a.k0, a.k1);
         double u1 = ((double)c[0] + 0.5) * 0x1p-32;
         double u2 = ((double)c[1] + 0.5) * 0x1p-32;
@@ -470,8 +472,9 @@ void scale_cols(double *a, long rows, int cols, long ld, const double *sg, hipSt
 }
 
 void philox_sketch(double *out, uint64_t seed, int step, uint32_t instance, const std::vector<int> &jdims,
-                   int chi, int m, int layout_jbm, hipStream_t st) {
+                   int chi, int m, int layout_jbm, hipStream_t st, const int *step_dev) {
     SketchArgs a{};
+    a.stepp = step_dev;
     a.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
     a.k1 = (uint32_t)(seed >> 32);
     a.instance = instance;

@@ -11,8 +11,10 @@
 // Every truncation keeps at most its cap, drops values at or below the
 // relative threshold and never cuts a multiplet (kept_count); kept vectors
 // get the sign convention of the weight w(multi-index).
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 
@@ -35,9 +37,20 @@ struct trg_state {
     double *dscal = nullptr;   // [0] logacc, [1] trace, [3] logacc before the step, [4..6) Gu-Wen traces,
                                // [6] norm c_k of the last re-split, [8..11) impurity traces,
                                // [1024..2048) trace partials
-    int *dint = nullptr;       // [0] numerical status, [1] status before the step, [8..] kept counts
+    int *dint = nullptr;       // [0] numerical status, [1] status before the step, [2] step index k,
+                               // [8..] kept counts
     std::vector<double> sigma_last;    // bond-swap singular values of the last step
     std::vector<double> resplit_last;  // re-split singular values / c_k of the last step
+    // the same two spectra on the device ([0, 1024) sigma, [1024, 2048) re-split);
+    // after a graph launch the host copies are refreshed from here on demand
+    double *dspec = nullptr;
+    bool spec_stale = false;
+    size_t nsig = 0, nrsv = 0;
+    // graph capture: most sweeps an eager step's iterative solve took, keyed by
+    // (call order in the step, batch count, m, n); capture_on while a step is recorded
+    std::map<std::array<int, 4>, int> sweep_log;
+    bool capture_on = false;
+    unsigned long gen = 0;   // bumped when device buffers a graph may hold are replaced
     std::string err;
     bool timing = false;
     double t_ms = 0.0, t_flops = 0.0;
@@ -53,8 +66,11 @@ constexpr double EPS_S = 1e-14, EPS_LAM = 1e-14, EPS_SQ = 1e-14, TAU_DEG_DEFAULT
 constexpr double PCHOL_TOL = 2.220446049250313e-16;
 
 // ---------------------------------------------------------------- small kernels
-__global__ void resplit_norm_kernel(double *s, int n, int k, double *logacc, double eps, int *status, double *cout) {
+// kp: the step index k (device)
+__global__ void resplit_norm_kernel(double *s, int n, const int *kp, double *logacc, double eps, int *status,
+                                    double *cout) {
     if (threadIdx.x || blockIdx.x) return;
+    const int k = *kp;
     double c = s[0];
     if (!(c > 0.0) || !isfinite(c)) {
         *status = 1;
@@ -207,7 +223,10 @@ struct Step {
         c.st = s->st;
         c.ar = &s->ar;
         c.prec = (Prec)s->opt.precision;
-        c.timing = s->timing;
+        c.timing = s->timing && !s->capture_on;
+        c.capture = s->capture_on;
+        c.dstatus = s->dint;
+        c.sweep_log = &s->sweep_log;
         kept = s->dint + 8;
     }
     int *new_kept() { return kept++; }
@@ -226,6 +245,33 @@ void col_slice(Ctx &c, const double *src, long rows, long cols, int k, double *d
                                    hipMemcpyDeviceToDevice, c.st));
 }
 
+// One-sided Jacobi under the step's convergence policy.  Eager: the host reads
+// every sweep's rotation count and the sweeps used are logged for the solve
+// (its call order in the step and its shape).  Captured: nothing is read back;
+// the panel solver runs device-driven up to 1.5 times the most sweeps logged
+// for the same solve, plus 4 (status 3 if that is not enough), the one-launch
+// solver up to max_sweeps as eagerly.
+int run_jacobi(Ctx &c, const JacobiBatch &jb, int ms, int *flags, double *work) {
+    const std::array<int, 4> key{c.solve_idx++, jb.count, jb.m, jb.n};
+    if (!c.capture) {
+        const int sw = jacobi_svd(jb, ms, flags, work, c.st);
+        if (c.sweep_log) {
+            int &v = (*c.sweep_log)[key];
+            v = std::max(v, sw + 1);
+        }
+        return sw;
+    }
+    int cap = ms;
+    if (jb.n > 96) {
+        auto it = c.sweep_log ? c.sweep_log->find(key) : std::map<std::array<int, 4>, int>::iterator();
+        TRG_REQUIRE(c.sweep_log && it != c.sweep_log->end(), TRG_E_STATE,
+                    "graph capture: no eager step of this method at these shapes has run on the state");
+        cap = std::min(ms, it->second + it->second / 2 + 4);
+    }
+    DevLoop dl{cap, c.dstatus, 3};
+    return jacobi_svd(jb, ms, flags, work, c.st, &dl);
+}
+
 // SVD of `count` matrices given column-major (a + i*m*n holds n columns of m):
 // s (count x n) descending, u (count x m x n) and v (count x n x n) row-major, sorted.
 void svd_colmajor(Step &T, const double *a, int count, int m, int n, double *s, double *u, double *v) {
@@ -234,10 +280,10 @@ void svd_colmajor(Step &T, const double *a, int count, int m, int n, double *s, 
     copy(ut, a, (size_t)count * m * n, c.st);
     double *vt = v ? c.ar->dalloc((size_t)count * n * n) : nullptr;   // no V wanted: not accumulated
     double *work = c.ar->dalloc((size_t)count * (n + 1));
-    int *flags = reinterpret_cast<int *>(c.ar->dalloc((size_t)count));   // 2 * count ints
+    int *flags = reinterpret_cast<int *>(c.ar->dalloc((size_t)count + 1));   // 2 * count + 1 ints
     JacobiBatch jb{count, m, n, ut, vt, (long)m * n, (long)n * n};
     int ms = T.S->opt.max_sweeps > 0 ? T.S->opt.max_sweeps : 300;
-    jacobi_svd(jb, ms, flags, work, c.st);
+    run_jacobi(c, jb, ms, flags, work);
     jacobi_finish(jb, s, u, v, work, c.st);
 }
 
@@ -273,16 +319,17 @@ bool gram_eig_pchol(Ctx &c, const double *k, int count, int n, int max_sweeps, d
     double *kw = c.ar->dalloc(count * nn), *xs = c.ar->dalloc(count * nn);
     copy(kw, k, count * nn, c.st);
     int *piws = reinterpret_cast<int *>(c.ar->dalloc((pchol_iws_ints(count, n) + 1) / 2));
-    if (!pivoted_cholesky_batched(kw, count, n, xs, piws, c.st, PCHOL_TOL)) {
+    if (!pivoted_cholesky_batched(kw, count, n, xs, piws, c.st, PCHOL_TOL, nullptr,
+                                  c.capture ? c.dstatus : nullptr)) {
         c.ar->release(mk);
         return false;
     }
     // the one-sided solver takes column-major matrices: X^T row-major
     permute(xs, kw, {count, n, n}, {0, 2, 1}, c.st);
     double *work = c.ar->dalloc((size_t)count * (n + 1)), *s = c.ar->dalloc((size_t)count * n);
-    int *flags = reinterpret_cast<int *>(c.ar->dalloc((size_t)count));   // 2 * count ints
+    int *flags = reinterpret_cast<int *>(c.ar->dalloc((size_t)count + 1));   // 2 * count + 1 ints
     JacobiBatch jb{count, n, n, kw, nullptr, (long)nn, (long)nn};
-    const int sw = jacobi_svd(jb, max_sweeps, flags, work, c.st);
+    const int sw = run_jacobi(c, jb, max_sweeps, flags, work);
     jacobi_finish(jb, s, vec, nullptr, work, c.st);
     hipLaunchKernelGGL(square_kernel, dim3(g1(count * n)), dim3(256), 0, c.st, s, lam, count * n);
     TRG_HIP_CHECK(hipGetLastError());
@@ -315,8 +362,8 @@ Split resplit(Step &T, const std::vector<int> &order) {
     DT w = contract(c, r1, "ia", r2, "ja", "ij");
     DT s = talloc(c, {chi}), u = talloc(c, {chi, chi}), v = talloc(c, {chi, chi});
     svd_rowmajor(T, w, s.p, u.p, v.p);
-    hipLaunchKernelGGL(resplit_norm_kernel, dim3(1), dim3(1), 0, c.st, s.p, chi, S->k, S->dscal, EPS_S, S->dint,
-                       S->dscal + 6);
+    hipLaunchKernelGGL(resplit_norm_kernel, dim3(1), dim3(1), 0, c.st, s.p, chi, S->dint + 2, S->dscal, EPS_S,
+                       S->dint, S->dscal + 6);
     DT A = contract(c, q1, "Fa", u, "ab", "Fb");
     DT Dm = contract(c, q2, "Fa", v, "ab", "Fb");
     // canonical bond basis: rotation within multiplets of s, B = Dm S', C = A S'
@@ -432,7 +479,7 @@ Swap bond_swap(Step &T, const Split &sp) {
     Bp.d = {(int)J, x, chi};
     Cp.d = {(int)I, x, chi};
     DT om = talloc(c, {(int)J, chi, m});
-    philox_sketch(om.p, S->opt.seed, S->k, S->opt.instance, td, chi, m, 1, c.st);
+    philox_sketch(om.p, S->opt.seed, S->k, S->opt.instance, td, chi, m, 1, c.st, S->dint + 2);
     DT Q = talloc(c, {(int)(I * chi), m}), Qp = talloc(c, {(int)(J * chi), m}), Rp = talloc(c, {m, m}), Rq = talloc(c, {m, m});
     double *ws = c.ar->dalloc(std::max(tsqr_ws_doubles(I * chi, m), tsqr_ws_doubles(J * chi, m)));
     DT cur = om;
@@ -572,8 +619,10 @@ void squeezers(Step &T, const double *kf, const double *kb, int cnt, int dt, int
         double *kw = c.ar->dalloc(2 * cnt * nn);
         copy(kw, kk, 2 * cnt * nn, c.st);
         int *piws = reinterpret_cast<int *>(c.ar->dalloc((pchol_iws_ints(2 * cnt, n) + 1) / 2));
-        chol_ok = pivoted_cholesky_batched(kw, 2 * cnt, n, xs, piws, c.st, PCHOL_TOL);
+        chol_ok = pivoted_cholesky_batched(kw, 2 * cnt, n, xs, piws, c.st, PCHOL_TOL, nullptr,
+                                           c.capture ? c.dstatus : nullptr);
     } else {
+        TRG_REQUIRE(!c.capture, TRG_E_UNSUPPORTED, "graph capture: squeezer Grams above 1024 are not supported");
         copy(xs, kk, 2 * cnt * nn, c.st);
         int *cst = reinterpret_cast<int *>(c.ar->dalloc(cnt + 1));
         double *cws = c.ar->dalloc(chol_ws_doubles(2 * cnt, n));
@@ -1067,6 +1116,23 @@ void triad_tangent(Step &T, const Split &sp, const Swap &sw, const TriadKeep &K,
     axpy_scale(c, dpsi_out, &t3, 1.0, nullptr);
 }
 
+// numerical status flag (dint[0]) -> error
+void check_status(int status) {
+    TRG_REQUIRE(status != 1, TRG_E_NUMERICAL, "non-positive or non-finite norm at a re-split");
+    TRG_REQUIRE(status != 2, TRG_E_MULTIPLET,
+                "a truncation cut falls in a multiplet of more than 16 values (canonical basis not formed); "
+                "change tau_deg or D");
+    TRG_REQUIRE(status != 3, TRG_E_NUMERICAL,
+                "Jacobi SVD of a replayed step: non-finite entries, or not converged within the sweeps "
+                "allowed at capture");
+    TRG_REQUIRE(status != 4, TRG_E_NUMERICAL, "pivoted Cholesky of a replayed step met a non-finite pivot");
+    TRG_REQUIRE(status == 0, TRG_E_NUMERICAL, "numerical status flag set");
+}
+
+__global__ void step_inc_kernel(int *k) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *k += 1;
+}
+
 // ---------------------------------------------------------------- one step
 void do_step(trg_state *S, int axis, bool triad) {
     TRG_REQUIRE(S->init, -2, "step before tensor_init");
@@ -1097,17 +1163,20 @@ void do_step(trg_state *S, int axis, bool triad) {
     stp += 'z';
     nat += 'z';
     TRG_REQUIRE((size_t)phi.n() <= S->cap_state && (size_t)psi.n() <= S->cap_state, -6, "state exceeds D^5");
-    // numerical status of the step (norm, multiplet sizes) before the state is overwritten
-    std::vector<double> sig(sw.sig.d[0], 0.0), rsv(sp.s.d[0], 0.0);
-    int status = 0;
-    TRG_HIP_CHECK(hipMemcpyAsync(sig.data(), sw.sig.p, sizeof(double) * sig.size(), hipMemcpyDeviceToHost, S->st));
-    TRG_HIP_CHECK(hipMemcpyAsync(rsv.data(), sp.s.p, sizeof(double) * rsv.size(), hipMemcpyDeviceToHost, S->st));
-    TRG_HIP_CHECK(hipMemcpyAsync(&status, S->dint, sizeof(int), hipMemcpyDeviceToHost, S->st));
-    TRG_HIP_CHECK(hipStreamSynchronize(S->st));
-    TRG_REQUIRE(status != 1, -4, "non-positive or non-finite norm at the re-split");
-    TRG_REQUIRE(status != 2, -4, "a truncation cut falls in a multiplet of more than 16 values (canonical basis "
-                                 "not formed); raise tau_deg's resolution or change D");
-    TRG_REQUIRE(status == 0, -4, "numerical status flag set");
+    const size_t nsig = sw.sig.d[0], nrsv = sp.s.d[0];
+    TRG_REQUIRE(nsig <= 1024 && nrsv <= 1024, -6, "spectra longer than 1024");
+    copy(S->dspec, sw.sig.p, nsig, S->st);
+    copy(S->dspec + 1024, sp.s.p, nrsv, S->st);
+    std::vector<double> sig(nsig, 0.0), rsv(nrsv, 0.0);
+    if (!T.c.capture) {
+        // numerical status of the step (norm, multiplet sizes) before the state is overwritten
+        int status = 0;
+        TRG_HIP_CHECK(hipMemcpyAsync(sig.data(), sw.sig.p, sizeof(double) * nsig, hipMemcpyDeviceToHost, S->st));
+        TRG_HIP_CHECK(hipMemcpyAsync(rsv.data(), sp.s.p, sizeof(double) * nrsv, hipMemcpyDeviceToHost, S->st));
+        TRG_HIP_CHECK(hipMemcpyAsync(&status, S->dint, sizeof(int), hipMemcpyDeviceToHost, S->st));
+        TRG_HIP_CHECK(hipStreamSynchronize(S->st));
+        check_status(status);
+    }
     std::vector<int> perm(d + 1);
     for (int i = 0; i <= d; ++i) perm[i] = (int)stp.find(nat[i]);
     permute(phi.p, S->phi, phi.d, perm, S->st);
@@ -1118,10 +1187,16 @@ void do_step(trg_state *S, int axis, bool triad) {
     }
     std::vector<int> nd(d);
     for (int i = 0; i < d; ++i) nd[i] = phi.d[perm[i]];
+    hipLaunchKernelGGL(step_inc_kernel, dim3(1), dim3(1), 0, S->st, S->dint + 2);
+    TRG_HIP_CHECK(hipGetLastError());
     S->dims = nd;
     S->chi = phi.d[d];
+    S->nsig = nsig;
+    S->nrsv = nrsv;
+    if (T.c.capture) return;   // the recorded step's host side ends here
     S->sigma_last = sig;
     S->resplit_last = rsv;
+    S->spec_stale = false;
     TRG_HIP_CHECK(hipStreamSynchronize(S->st));
     for (auto &t : T.c.timed) {
         float ms = 0.0f;
@@ -1200,6 +1275,7 @@ int trg_create(const trg_options *opt, trg_state **out) {
         s->ar.set_cap(opt->workspace_cap);
         TRG_HIP_CHECK(hipMalloc(&s->dscal, 2048 * sizeof(double)));
         TRG_HIP_CHECK(hipMalloc(&s->dint, 256 * sizeof(int)));
+        TRG_HIP_CHECK(hipMalloc(&s->dspec, 2048 * sizeof(double)));
     } catch (const Error &e) {
         g_err = e.what();
         trg_destroy(s);
@@ -1222,6 +1298,7 @@ int trg_destroy(trg_state *s) {
     }
     if (s->dscal) (void)hipFree(s->dscal);
     if (s->dint) (void)hipFree(s->dint);
+    if (s->dspec) (void)hipFree(s->dspec);
     delete s;
     return TRG_OK;
 }
@@ -1341,7 +1418,7 @@ int tensor_init(trg_state *s, int model, double beta, double h, int D) {
                                          hipMemcpyHostToDevice, st));
         }
         double zero[2] = {0.0, 0.0};
-        int izero[1] = {0};
+        int izero[4] = {0, 0, 0, 0};   // status, saved status, step index
         TRG_HIP_CHECK(hipMemcpyAsync(s->dscal, zero, sizeof(zero), hipMemcpyHostToDevice, st));
         TRG_HIP_CHECK(hipMemcpyAsync(s->dint, izero, sizeof(izero), hipMemcpyHostToDevice, st));
         TRG_HIP_CHECK(hipStreamSynchronize(st));
@@ -1355,6 +1432,9 @@ int tensor_init(trg_state *s, int model, double beta, double h, int D) {
         s->init = true;
         s->sigma_last.clear();
         s->resplit_last.clear();
+        s->spec_stale = false;
+        s->sweep_log.clear();
+        s->gen += 1;   // graphs captured before hold the old state's buffers and shapes
     } catch (const Error &e) {
         return fail(s, e);
     } catch (const std::exception &e) {
@@ -1411,6 +1491,120 @@ static int step_common(trg_state *s, int axis, bool triad) {
 int atrg_step(trg_state *s, int axis) { return step_common(s, axis, false); }
 int triad_atrg_step(trg_state *s, int axis) { return step_common(s, axis, true); }
 
+// ---------------------------------------------------------------- captured steps
+struct trg_graph {
+    trg_state *s = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned long gen = 0;
+    std::vector<int> dims_in, dims_out;
+    int chi_in = 0, chi_out = 0;
+    size_t nsig = 0, nrsv = 0;
+};
+
+int trg_graph_destroy(trg_graph *g) {
+    if (!g) return TRG_OK;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return TRG_OK;
+}
+
+// The step is recorded on a private stream (a capture cannot use the null
+// stream) with the host state put back afterwards: recording runs nothing, so
+// the tensors, k and the spectra stay those before the step.
+int trg_graph_capture(trg_state *s, int method, int axis, trg_graph **out) {
+    if (!s || !out || (method != TRG_METHOD_ATRG && method != TRG_METHOD_TRIAD)) return TRG_E_INVALID;
+    *out = nullptr;
+    if (!s->init) {
+        s->err = "capture before tensor_init";
+        return TRG_E_STATE;
+    }
+    if (axis < 0 || axis >= s->opt.dim) {
+        s->err = "axis out of range";
+        return TRG_E_INVALID;
+    }
+    trg_graph *g = new (std::nothrow) trg_graph();
+    if (!g) return TRG_E_NOMEM;
+    g->s = s;
+    g->gen = s->gen;
+    g->dims_in = s->dims;
+    g->chi_in = s->chi;
+    const hipStream_t user = s->st;
+    hipStream_t cs = nullptr;
+    bool capturing = false;
+    int rc = TRG_OK;
+    try {
+        DevGuard dg(s->opt.device);
+        TRG_HIP_CHECK(hipStreamSynchronize(user));
+        TRG_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        s->st = cs;
+        s->capture_on = true;
+        s->ar.freeze(true);
+        TRG_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        capturing = true;
+        trg::do_step(s, axis, method == TRG_METHOD_TRIAD);
+        capturing = false;
+        TRG_HIP_CHECK(hipStreamEndCapture(cs, &g->graph));
+        g->dims_out = s->dims;
+        g->chi_out = s->chi;
+        g->nsig = s->nsig;
+        g->nrsv = s->nrsv;
+        TRG_HIP_CHECK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    } catch (const Error &e) {
+        rc = fail(s, e);
+    } catch (const std::exception &e) {
+        rc = fail_std(s, e);
+    }
+    if (capturing) {
+        hipGraph_t partial = nullptr;
+        if (hipStreamEndCapture(cs, &partial) == hipSuccess && partial) (void)hipGraphDestroy(partial);
+        (void)hipGetLastError();
+    }
+    s->capture_on = false;
+    s->ar.freeze(false);
+    s->st = user;
+    s->dims = g->dims_in;
+    s->chi = g->chi_in;
+    if (cs) (void)hipStreamDestroy(cs);
+    if (rc != TRG_OK) {
+        trg_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return TRG_OK;
+}
+
+int trg_graph_launch(trg_graph *g) {
+    if (!g || !g->s || !g->exec) return TRG_E_INVALID;
+    trg_state *s = g->s;
+    if (!s->init || s->gen != g->gen) {
+        s->err = "graph recorded before the last tensor_init or trg_release_workspace";
+        return TRG_E_STATE;
+    }
+    if (s->dims != g->dims_in || s->chi != g->chi_in) {
+        s->err = "graph recorded at other shapes";
+        return TRG_E_STATE;
+    }
+    if (s->k >= 0xFFFF) {
+        s->err = "step index past the sketch counter's 16 bits";
+        return TRG_E_UNSUPPORTED;
+    }
+    try {
+        DevGuard dg(s->opt.device);
+        TRG_HIP_CHECK(hipGraphLaunch(g->exec, s->st));
+    } catch (const Error &e) {
+        return fail(s, e);
+    }
+    s->k += 1;
+    s->dims = g->dims_out;
+    s->chi = g->chi_out;
+    s->nsig = g->nsig;
+    s->nrsv = g->nrsv;
+    s->spec_stale = true;
+    return TRG_OK;
+}
+
 int log_z_per_site(trg_state *s, double *out) {
     if (!s || !out) return TRG_E_INVALID;
     if (!s->init) return TRG_E_STATE;
@@ -1426,8 +1620,7 @@ int log_z_per_site(trg_state *s, double *out) {
         TRG_HIP_CHECK(hipMemcpyAsync(hs, s->dscal, sizeof(hs), hipMemcpyDeviceToHost, s->st));
         TRG_HIP_CHECK(hipMemcpyAsync(&status, s->dint, sizeof(int), hipMemcpyDeviceToHost, s->st));
         TRG_HIP_CHECK(hipStreamSynchronize(s->st));
-        if (status == 1) throw Error(TRG_E_NUMERICAL, "non-positive or non-finite norm at a re-split");
-        if (status != 0) throw Error(TRG_E_NUMERICAL, "numerical status flag set by an earlier step");
+        trg::check_status(status);
         if (!(hs[1] > 0.0) || !std::isfinite(hs[1])) throw Error(TRG_E_NUMERICAL, "final trace is not positive");
         *out = hs[0] + std::ldexp(std::log(hs[1]), -s->k);
     } catch (const Error &e) {
@@ -1537,6 +1730,7 @@ int trg_release_workspace(trg_state *s) {
         DevGuard g(s->opt.device);
         TRG_HIP_CHECK(hipStreamSynchronize(s->st));
         s->ar.trim();
+        s->gen += 1;   // captured graphs held workspace addresses
     } catch (const Error &e) {
         return fail(s, e);
     }
@@ -1558,8 +1752,8 @@ size_t trg_export_size(trg_state *s, int which) {
     size_t n = (size_t)s->chi;
     for (int v : s->dims) n *= v;
     if (which == TRG_T_PHI || which == TRG_T_PSI) return n * sizeof(double);
-    if (which == TRG_T_SIGMA) return s->sigma_last.size() * sizeof(double);
-    if (which == TRG_T_RESPLIT) return s->resplit_last.size() * sizeof(double);
+    if (which == TRG_T_SIGMA) return (s->spec_stale ? s->nsig : s->sigma_last.size()) * sizeof(double);
+    if (which == TRG_T_RESPLIT) return (s->spec_stale ? s->nrsv : s->resplit_last.size()) * sizeof(double);
     return 0;
 }
 
@@ -1570,6 +1764,17 @@ int trg_export(trg_state *s, int which, void *dst, size_t bytes) {
     if (need == 0 || bytes != need) return TRG_E_INVALID;
     try {
         DevGuard g(s->opt.device);
+        if ((which == TRG_T_SIGMA || which == TRG_T_RESPLIT) && s->spec_stale) {
+            // spectra of a replayed step: from the device copies
+            std::vector<double> sig(s->nsig), rsv(s->nrsv);
+            TRG_HIP_CHECK(hipMemcpyAsync(sig.data(), s->dspec, sizeof(double) * s->nsig, hipMemcpyDeviceToHost, s->st));
+            TRG_HIP_CHECK(hipMemcpyAsync(rsv.data(), s->dspec + 1024, sizeof(double) * s->nrsv, hipMemcpyDeviceToHost,
+                                         s->st));
+            TRG_HIP_CHECK(hipStreamSynchronize(s->st));
+            s->sigma_last = sig;
+            s->resplit_last = rsv;
+            s->spec_stale = false;
+        }
         if (which == TRG_T_SIGMA) {
             std::memcpy(dst, s->sigma_last.data(), need);
             return TRG_OK;
@@ -1612,6 +1817,7 @@ const char *trg_strerror(int code) {
         case TRG_E_NUMERICAL: return "numerical failure";
         case TRG_E_HIP: return "HIP runtime error";
         case TRG_E_UNSUPPORTED: return "unsupported shape";
+        case TRG_E_MULTIPLET: return "truncation cut inside a multiplet too large for the canonical basis";
         default: return "unknown error";
     }
 }

@@ -1,0 +1,143 @@
+"""Captured RG steps (trg_graph_*): a replayed step equals the eager step bit for bit.
+
+Each case runs one solve eagerly and one through graphs: eager steps until a
+step leaves the shapes unchanged (that step sized the workspace and logged the
+Jacobi sweeps), then one recorded step per axis, replayed for the rest of the
+flow.  Every later log Z/V, the final (Phi, Psi), both spectra and, with
+tangents, the impurity derivatives must be identical, not merely close: the
+replay runs the same kernels in the same order on the same data.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2507_21909_amd as trg
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _step(s, method, axis):
+    if method == trg.METHOD_TRIAD:
+        s.triad_atrg_step(axis)
+    else:
+        s.atrg_step(axis)
+
+
+CASES = [
+    # (name, D, steps, method, solver options, beta, h)
+    ("triad_d8", 8, 14, trg.METHOD_TRIAD, {}, 0.1497, 0.0),
+    ("triad_d16", 16, 10, trg.METHOD_TRIAD, {}, 0.1497, 1e-4),
+    ("atrg_d8", 8, 12, trg.METHOD_ATRG, {}, 0.15, 0.0),
+    ("ilo_d12_rb2", 12, 9, trg.METHOD_TRIAD, {"r_bond": 2, "sketch_mult": 3}, 0.1497, 0.0),
+    ("tangents_d8", 8, 10, trg.METHOD_TRIAD, {"tangents": trg.TAN_BETA | trg.TAN_H}, 0.1497, 1e-3),
+    ("bf16x6_d16", 16, 8, trg.METHOD_TRIAD, {"precision": trg.BF16X6}, 0.1497, 1e-4),
+]
+
+
+@pytest.mark.parametrize("name,D,steps,method,opts,beta,h", CASES, ids=[c[0] for c in CASES])
+def test_graph_replay_bitwise(name, D, steps, method, opts, beta, h):
+    _say("graph replay", name)
+    eager = trg.Solver(seed=11, **opts)
+    eager.tensor_init(trg.MODEL_ISING, beta, h, D)
+    ref = []
+    for k in range(steps):
+        _step(eager, method, k % 4)
+        ref.append(eager.log_z_per_site())
+    ref_phi, ref_psi = eager.export(trg.T_PHI), eager.export(trg.T_PSI)
+    ref_sig, ref_rsv = eager.export(trg.T_SIGMA), eager.export(trg.T_RESPLIT)
+    ref_der = eager.impurity_derivatives() if opts.get("tangents") else None
+
+    s = trg.Solver(seed=11, **opts)
+    s.tensor_init(trg.MODEL_ISING, beta, h, D)
+    k = 0
+    while True:
+        before = s.shape()[:2]
+        _step(s, method, k % 4)
+        assert s.log_z_per_site() == ref[k]
+        k += 1
+        if s.shape()[:2] == before:
+            break
+    assert k < steps - 2, "shapes still changing: too few steps for a replay"
+    graphs = [s.capture(a, method) for a in range(4)]
+    assert s.shape()[2] == k   # recording runs nothing
+    _say("  eager steps", k, "then replays")
+    for kk in range(k, steps):
+        graphs[kk % 4].launch()
+        got = s.log_z_per_site()
+        assert got == ref[kk], (kk, got, ref[kk])
+    assert s.shape()[2] == steps
+    assert np.array_equal(s.export(trg.T_PHI), ref_phi)
+    assert np.array_equal(s.export(trg.T_PSI), ref_psi)
+    assert np.array_equal(s.export(trg.T_SIGMA), ref_sig)
+    assert np.array_equal(s.export(trg.T_RESPLIT), ref_rsv)
+    if ref_der is not None:
+        assert s.impurity_derivatives() == ref_der
+    for g in graphs:
+        g.close()
+
+
+def test_graph_launches_back_to_back():
+    """Launches queued without a synchronisation between them end in the eager flow's state."""
+    _say("graph back-to-back")
+    D, steps = 12, 12
+    eager = trg.Solver(seed=3)
+    eager.tensor_init(trg.MODEL_ISING, 0.1497, 0.0, D)
+    for k in range(steps):
+        eager.triad_atrg_step(k % 4)
+    s = trg.Solver(seed=3)
+    s.tensor_init(trg.MODEL_ISING, 0.1497, 0.0, D)
+    k = 0
+    while True:
+        before = s.shape()[:2]
+        s.triad_atrg_step(k % 4)
+        k += 1
+        if s.shape()[:2] == before:
+            break
+    graphs = [s.capture(a) for a in range(4)]
+    for kk in range(k, steps):
+        graphs[kk % 4].launch()
+    assert s.log_z_per_site() == eager.log_z_per_site()
+    assert np.array_equal(s.export(trg.T_PHI), eager.export(trg.T_PHI))
+
+
+def test_graph_state_rules():
+    """Capture needs an eager step at the current shapes; tensor_init and workspace release retire graphs."""
+    _say("graph state rules")
+    s = trg.Solver(seed=1)
+    with pytest.raises(trg.TrgError) as ei:
+        s.capture(0)
+    assert ei.value.code == -2   # before tensor_init
+    s.tensor_init(trg.MODEL_ISING, 0.1497, 0.0, 6)
+    with pytest.raises(trg.TrgError) as ei:
+        s.capture(0)
+    assert ei.value.code == -2   # no eager step has sized the workspace
+    assert s.shape()[2] == 0
+    for k in range(6):
+        s.triad_atrg_step(k % 4)
+    lz = s.log_z_per_site()
+    g = s.capture(2)
+    assert s.shape()[2] == 6 and s.log_z_per_site() == lz
+    g.launch()
+    assert s.shape()[2] == 7
+    s.release_workspace()
+    with pytest.raises(trg.TrgError) as ei:
+        g.launch()
+    assert ei.value.code == -2
+    g.close()
+    s.triad_atrg_step(3)   # eager steps still work and size the workspace again
+    g = s.capture(0)
+    g.launch()
+    s.tensor_init(trg.MODEL_ISING, 0.1497, 0.0, 6)
+    with pytest.raises(trg.TrgError) as ei:
+        g.launch()
+    assert ei.value.code == -2
+    g.close()
+    with pytest.raises(trg.TrgError) as ei:
+        s.capture(0, method=5)
+    assert ei.value.code == -1

@@ -43,9 +43,14 @@ def test_failed_reinit_invalidates_state():
     s = trg.Solver(seed=5)
     s.tensor_init(trg.MODEL_ISING, 0.1497, 0.0, 4)
     s.triad_atrg_step(0)
-    # D = 400: two D^5 FP64 tensors of 82 TB each cannot be allocated
+    # D = 400 is outside the kernels' limits: refused before anything changes
     with pytest.raises(trg.TrgError) as ei:
         s.tensor_init(trg.MODEL_ISING, 0.1497, 0.0, 400)
+    assert ei.value.code == -6
+    s.log_z_per_site()
+    # D = 200: two D^5 FP64 tensors of 2.6 TB each cannot be allocated
+    with pytest.raises(trg.TrgError) as ei:
+        s.tensor_init(trg.MODEL_ISING, 0.1497, 0.0, 200)
     assert ei.value.code == -3
     with pytest.raises(trg.TrgError) as ei:
         s.triad_atrg_step(1)
