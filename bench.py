@@ -66,9 +66,12 @@ def cpu_baseline(D, r, beta, h, seed):
 def batch_main(args):
     """The 128-instance parameter scan (the T_c search workload): beta_j = 0.140 + 0.020 j / 31
     (j = 0..31) x h_l in {0, 1e-4, 1e-3, 1e-2}, instance i = j + 32 l, D = (8, 12, 16, 24)[i mod 4],
-    r = 7, L = 2^10 per axis (40 steps).  One trg_batch_run against lone solves of a sample of the
-    instances (bit-for-bit equality checked), and the sequential time of all 128 estimated from
-    the sample's per-D step times.  The batch runs one axis cycle (4 steps) per call."""
+    r = 7, L = 2^10 per axis (40 steps).  The 128 instances run as four trg_batch objects of 32
+    (instance words 0, 32, 64, 96, so every instance draws the sketches it would in one batch of
+    128), first eagerly (trg_batch_run), then with the steady steps replayed from HIP graphs
+    (trg_batch_run_graphs); the two must agree bit for bit, and a sample of instances must equal
+    lone solves bit for bit.  The sequential time of all 128 is estimated from the sample's per-D
+    times."""
     import numpy as np
     import paper_2507_21909_amd as trg
     seed = 0x2507219090000000 + 4000
@@ -79,43 +82,76 @@ def batch_main(args):
         hs.append([0.0, 1e-4, 1e-3, 1e-2][l])
         Ds.append([8, 12, 16, 24][i % 4])
     nsteps = args.batch_steps
-    b = trg.Batch(betas, hs, Ds, seed=seed)
-    print("batch of 128 created", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    done = 0
-    while done < nsteps:   # one call per axis cycle, so the run reports its progress
-        k = min(4, nsteps - done)
-        b.run(k, axes=[(done + i) % 4 for i in range(k)])
-        done += k
-        print("batch: %d of %d steps done" % (done, nsteps), file=sys.stderr, flush=True)
-    got = b.log_z_per_site()
-    t_batch = time.perf_counter() - t0
-    print("batch run done in %.1f s" % t_batch, file=sys.stderr, flush=True)
-    b.close()
+
+    def run(graphs):
+        out = np.empty(128)
+        wall = 0.0
+        for g in range(4):
+            idx = slice(32 * g, 32 * g + 32)
+            b = trg.Batch(betas[idx], hs[idx], Ds[idx], seed=seed, instance=32 * g)
+            t0 = time.perf_counter()
+            b.run(nsteps, graphs=graphs)
+            out[idx] = b.log_z_per_site()
+            wall += time.perf_counter() - t0
+            b.close()
+            print("batch (%s): instances %d..%d done, %.1f s" % ("graphs" if graphs else "eager", 32 * g,
+                                                                 32 * g + 31, wall), file=sys.stderr, flush=True)
+        return out, wall
+
+    got_e, t_eager = run(False)
+    got, t_graph = run(True)
+    if not np.array_equal(got, got_e):
+        bad = int(np.flatnonzero(got != got_e)[0])
+        print("graph batch differs from the eager batch at instance %d" % bad, file=sys.stderr)
+        sys.exit(1)
     sample = [0, 1, 2, 3, 45, 46, 47, 60, 66, 79, 93, 98, 103, 113, 126, 127]
-    t_by_d = {}
-    for i in sample:
+    t_by_d, tg_by_d = {}, {}
+
+    def lone(i, graphs):
         s = trg.Solver(seed=seed, instance=i)
         s.tensor_init(trg.MODEL_ISING, betas[i], hs[i], Ds[i])
         t0 = time.perf_counter()
-        for k in range(nsteps):
+        rec, k = None, 0
+        while k < nsteps:
+            if rec:
+                rec[k % 4].launch()     # unchecked: the status is read at the end
+                k += 1
+                continue
+            before = s.shape()[:2]
             s.triad_atrg_step(k % 4)
+            k += 1
+            if graphs and s.shape()[:2] == before and k < nsteps:
+                rec = [s.capture(a) for a in range(4)]
         f = s.log_z_per_site()
-        t_by_d.setdefault(Ds[i], []).append(time.perf_counter() - t0)
+        dt = time.perf_counter() - t0
+        for g in rec or []:
+            g.close()
         s.close()
-        print("lone solve of instance %d (D=%d) done" % (i, Ds[i]), file=sys.stderr, flush=True)
-        if f != got[i]:
-            print("instance %d differs: batch %.17g alone %.17g" % (i, got[i], f), file=sys.stderr)
+        return f, dt
+
+    for i in sample:
+        f, dt = lone(i, False)
+        t_by_d.setdefault(Ds[i], []).append(dt)
+        fg, dtg = lone(i, True)
+        tg_by_d.setdefault(Ds[i], []).append(dtg)
+        print("lone solves of instance %d (D=%d) done: eager %.3f s, graphs %.3f s" % (i, Ds[i], dt, dtg),
+              file=sys.stderr, flush=True)
+        if f != got[i] or fg != got[i]:
+            print("instance %d differs: batch %.17g alone %.17g graphs %.17g" % (i, got[i], f, fg), file=sys.stderr)
             sys.exit(1)
     t_seq = sum(32 * float(np.mean(v)) for v in t_by_d.values())
     out = {"metric": "batched triad-ATRG instance-steps/s (128 instances, D in {8,12,16,24})",
-           "value": 128 * nsteps / t_batch, "unit": "instance-steps/s", "n_gpus": 1, "steps": nsteps,
+           "value": 128 * nsteps / t_graph, "unit": "instance-steps/s", "n_gpus": 1, "steps": nsteps,
            "higher_is_better": True, "dtype": "f64", "data": "synthetic (4D Ising tensors from beta, h)",
-           "config": {"workload": "128-instance beta x h scan, r=7, %d steps" % nsteps},
-           "batch_wall_s": t_batch, "sequential_wall_s_estimated": t_seq,
+           "config": {"workload": "128-instance beta x h scan, r=7, %d steps, steady steps replayed "
+                                  "from HIP graphs" % nsteps},
+           "batch_wall_s": t_graph, "eager_batch_wall_s": t_eager,
+           "eager_instance_steps_per_s": 128 * nsteps / t_eager,
+           "sequential_wall_s_estimated": t_seq,
            "sequential_instance_steps_per_s": 128 * nsteps / t_seq,
            "sequential_s_per_solve_by_D": {str(k): float(np.mean(v)) for k, v in sorted(t_by_d.items())},
-           "bitwise_equal_sample": len(sample)}
+           "lone_graph_s_per_solve_by_D": {str(k): float(np.mean(v)) for k, v in sorted(tg_by_d.items())},
+           "graphs_equal_eager_bitwise": 128, "bitwise_equal_sample": len(sample)}
     print(json.dumps(out), flush=True)
 
 
@@ -185,6 +221,8 @@ def main():
     ap.add_argument("--derivatives", action="store_true",
                     help="internal energy / magnetisation scan by the impurity tangents (use --D 24)")
     ap.add_argument("--derivative-points", type=int, default=16)
+    ap.add_argument("--graphs", action="store_true",
+                    help="time steps replayed from HIP graphs recorded after the warmup (no kernel timing)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the RG step on a single MI355X "
@@ -206,10 +244,24 @@ def main():
         s.triad_atrg_step(i % 4)
         print("warmup step %d done, dims %s" % (i, s.shape()[0]), file=sys.stderr, flush=True)
     s.log_z_per_site()                 # synchronises the stream
-    s.set_timing(True)
-    s.kernel_time()                    # reset counters
+    graphs = None
+    if args.graphs:
+        before = s.shape()[:2]
+        s.triad_atrg_step(args.warmup % 4)   # one more eager step: it must leave the shapes unchanged
+        args.warmup += 1
+        if s.shape()[:2] != before:
+            print("shapes still changing after the warmup: raise --warmup", file=sys.stderr)
+            sys.exit(1)
+        graphs = [s.capture(a) for a in range(4)]
+        print("4 steps recorded", file=sys.stderr, flush=True)
+    else:
+        s.set_timing(True)
+        s.kernel_time()                # reset counters
     t0 = time.perf_counter()
     for i in range(args.warmup, args.warmup + args.steps):
+        if graphs:
+            graphs[i % 4].launch()
+            continue
         s.triad_atrg_step(i % 4)
         print("timed step %d done" % i, file=sys.stderr, flush=True)
     f = s.log_z_per_site()             # synchronises the stream
@@ -241,8 +293,9 @@ def main():
         "dtype": DTYPE[args.precision],
         "data": "synthetic (4D Ising tensor from beta, h; seeded Philox sketch)",
         "config": {"workload": "triad-ATRG 4D Ising, beta=%g, h=%g, D=%d, r=%d (R=%d), sketch 2D, 1 power "
-                               "iteration, steady-state steps %d..%d of the flow" % (
-                                   args.beta, args.h, args.D, args.r, R, args.warmup, args.warmup + args.steps - 1),
+                               "iteration, steady-state steps %d..%d of the flow%s" % (
+                                   args.beta, args.h, args.D, args.r, R, args.warmup, args.warmup + args.steps - 1,
+                                   ", replayed from HIP graphs" if graphs else ""),
                    "D": args.D, "R": R, "precision": args.precision},
         "makeMG_makeMH_tflops_over_step_time": step_flops / (ms_step * 1e-3) / 1e12,
         "log_z_per_site": f,

@@ -189,14 +189,21 @@ int trg_release_workspace(trg_state *s);
  * n > 1024 squeezer Gram nor the eigensolver fallback can be recorded
  * (TRG_E_UNSUPPORTED).
  *
- * trg_graph_launch enqueues the recorded step on the state's stream and
- * returns without waiting; the state then holds the next step's tensors,
- * step count, spectra and log-norm, bit for bit those of the eager step
- * (same kernels in the same order).  A failure inside a launched step is
+ * trg_graph_launch enqueues the recorded step on the state's stream; the
+ * state then holds the next step's tensors, step count, spectra and
+ * log-norm, bit for bit those of the eager step (same kernels in the same
+ * order).  check = 0: returns without waiting; a failure inside the step
+ * (including a Jacobi solve that needs more sweeps than recorded) is
  * reported by the next call that reads the status (log_z_per_site) as
- * TRG_E_NUMERICAL or TRG_E_MULTIPLET, with no rollback.  TRG_E_STATE if the
- * state's shapes differ from those at capture, or if tensor_init or
- * trg_release_workspace ran on the state since the capture.
+ * TRG_E_NUMERICAL or TRG_E_MULTIPLET, with no rollback.  check != 0: waits
+ * for the step and reads its status; on a failure the state goes back to
+ * where the step started (the recorded step keeps a copy of it) and the
+ * error is returned, as for an eager step, so the caller can take that step
+ * eagerly (which logs the sweeps it needed) and record again.  TRG_E_STATE
+ * if the state's shapes differ from those at capture, or if tensor_init or
+ * trg_release_workspace ran on the state since the capture.  Recording
+ * allocates that copy once per state (twice the state tensors, tangents
+ * included).
  *
  * trg_graph_destroy frees a graph (NULL: no-op); destroy graphs before their
  * state.  One graph per (method, axis) covers a steady RG loop: the shapes
@@ -206,7 +213,7 @@ int trg_release_workspace(trg_state *s);
 #define TRG_METHOD_TRIAD 1
 typedef struct trg_graph trg_graph;
 int trg_graph_capture(trg_state *s, int method, int axis, trg_graph **out);
-int trg_graph_launch(trg_graph *g);
+int trg_graph_launch(trg_graph *g, int check);
 int trg_graph_destroy(trg_graph *g);
 
 /* ---- many instances ------------------------------------------------------ */
@@ -234,6 +241,17 @@ int trg_batch_create(int n, const double *betas, const double *hs, const int *Ds
  * instance is returned (trg_batch_last_error names the instance).
  */
 int trg_batch_run(trg_batch *b, int nsteps, const int *axes);
+
+/*
+ * trg_batch_run_graphs -- trg_batch_run with the steady part of each flow
+ * replayed from HIP graphs: an instance steps eagerly until a step leaves
+ * its shapes unchanged, then records one step per axis (trg_graph_capture)
+ * and replays them for its remaining steps, checked (one status read per
+ * step instead of one per Jacobi sweep).  A replay that fails is rolled
+ * back and taken eagerly, and the steps are recorded again; the graphs are
+ * destroyed when the instance is done.  Same bits as trg_batch_run.
+ */
+int trg_batch_run_graphs(trg_batch *b, int nsteps, const int *axes);
 
 /* log Z / V of every instance into out_n[0..n) (host).  Synchronises. */
 int trg_batch_log_z(trg_batch *b, double *out_n);

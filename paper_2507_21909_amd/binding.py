@@ -91,6 +91,8 @@ def load_library(path=None):
     lib.trg_batch_create.argtypes = [ctypes.c_int, _DP, _DP, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
                                      ctypes.POINTER(ctypes.c_void_p)]
     lib.trg_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.trg_batch_run_graphs.argtypes = lib.trg_batch_run.argtypes
+    lib.trg_batch_run_graphs.restype = ctypes.c_int
     lib.trg_batch_log_z.argtypes = [ctypes.c_void_p, _DP]
     lib.trg_batch_size.argtypes = [ctypes.c_void_p]
     lib.trg_batch_last_error.argtypes = [ctypes.c_void_p]
@@ -104,7 +106,7 @@ def load_library(path=None):
     lib.trg_release_workspace.argtypes = [st]
     lib.trg_release_workspace.restype = ctypes.c_int
     lib.trg_graph_capture.argtypes = [st, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
-    lib.trg_graph_launch.argtypes = [ctypes.c_void_p]
+    lib.trg_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.trg_graph_destroy.argtypes = [ctypes.c_void_p]
     for f in ("trg_graph_capture", "trg_graph_launch", "trg_graph_destroy"):
         getattr(lib, f).restype = ctypes.c_int
@@ -231,8 +233,9 @@ class Graph:
         self._solver = solver   # destroyed before the solver: keep it alive
         self._g = handle
 
-    def launch(self):
-        _check(self._solver._lib.trg_graph_launch(self._g), self._solver._s)
+    def launch(self, check=False):
+        """Replay the step (trg_graph_launch); check=True waits, and rolls a failed step back."""
+        _check(self._solver._lib.trg_graph_launch(self._g, 1 if check else 0), self._solver._s)
 
     def close(self):
         if self._g:
@@ -275,11 +278,13 @@ class Batch:
             raise TrgError(rc, "%s (%s)" % (self._lib.trg_strerror(rc).decode(),
                                             self._lib.trg_batch_last_error(self._b).decode()))
 
-    def run(self, nsteps, axes=None):
+    def run(self, nsteps, axes=None, graphs=False):
+        """nsteps steps of every instance (trg_batch_run, or trg_batch_run_graphs with graphs=True)."""
         ax = None if axes is None else (ctypes.c_int * len(axes))(*axes)
         if axes is not None and len(axes) != nsteps:
             raise ValueError("axes must list one axis per step")
-        self._check(self._lib.trg_batch_run(self._b, nsteps, ax))
+        f = self._lib.trg_batch_run_graphs if graphs else self._lib.trg_batch_run
+        self._check(f(self._b, nsteps, ax))
 
     def log_z_per_site(self):
         out = np.empty(self.n)

@@ -8,6 +8,11 @@
 // D instances are latency-bound, and this overlap is where the throughput
 // comes from.  The kernels are the single-instance kernels, so every instance
 // gives bit for bit what a lone solver with the same options gives.
+// trg_batch_run_graphs takes the host out of the steady part of each flow:
+// once a step leaves an instance's shapes unchanged, one recorded step per
+// axis (trg_graph_capture) is replayed for the rest of its steps, with one
+// status read per step instead of one per Jacobi sweep; replays equal eager
+// steps bit for bit.
 #include <algorithm>
 #include <atomic>
 #include <string>
@@ -30,7 +35,85 @@ struct trg_batch {
 
 namespace {
 constexpr int MAX_WORKERS = 8;
+
+// all nsteps of one instance: eager steps, and with graphs, checked replays of
+// recorded steps from the first step that leaves the shapes unchanged; a
+// replay that fails is rolled back by the library and the step taken eagerly
+// (an error there is the instance's error), then the steps are recorded again
+int run_instance(trg_state *s, int nsteps, const int *axes, bool graphs) {
+    trg_graph *g[4] = {nullptr, nullptr, nullptr, nullptr};
+    auto drop = [&]() {
+        for (trg_graph *&x : g) {
+            trg_graph_destroy(x);
+            x = nullptr;
+        }
+    };
+    auto record = [&]() {
+        int rc = TRG_OK;
+        for (int a = 0; a < 4 && rc == TRG_OK; ++a) rc = trg_graph_capture(s, TRG_METHOD_TRIAD, a, &g[a]);
+        if (rc != TRG_OK) drop();
+        return rc;
+    };
+    bool steady = false;
+    int rc = TRG_OK;
+    for (int k = 0; k < nsteps && rc == TRG_OK; ++k) {
+        const int ax = axes ? axes[k] : k % 4;
+        if (steady) {
+            if (trg_graph_launch(g[ax], 1) == TRG_OK) continue;
+            drop();
+            rc = triad_atrg_step(s, ax);
+            if (rc == TRG_OK && k + 1 < nsteps) rc = record();
+            continue;
+        }
+        int d0[4], c0 = 0, d1[4], c1 = 0;
+        if (graphs) rc = trg_shape(s, d0, &c0, nullptr);
+        if (rc == TRG_OK) rc = triad_atrg_step(s, ax);
+        if (rc == TRG_OK && graphs) {
+            rc = trg_shape(s, d1, &c1, nullptr);
+            if (rc == TRG_OK && c0 == c1 && std::equal(d0, d0 + 4, d1) && k + 1 < nsteps) {
+                rc = record();
+                steady = rc == TRG_OK;
+            }
+        }
+    }
+    drop();
+    return rc;
 }
+
+int run_all(trg_batch *b, int nsteps, const int *axes, bool graphs) {
+    if (!b || nsteps < 0) return TRG_E_INVALID;
+    if (axes)
+        for (int i = 0; i < nsteps; ++i)
+            if (axes[i] < 0 || axes[i] > 3) return TRG_E_INVALID;
+    const int n = (int)b->s.size();
+    std::atomic<int> next{0};
+    std::atomic<int> first_rc{TRG_OK};
+    std::vector<std::string> errs(n);
+    auto work = [&]() {
+        (void)hipSetDevice(b->device);
+        for (int i = next++; i < n; i = next++) {
+            const int rc = run_instance(b->s[i], nsteps, axes, graphs);
+            if (rc != TRG_OK) {
+                errs[i] = trg_last_error(b->s[i]);
+                int expect = TRG_OK;
+                first_rc.compare_exchange_strong(expect, rc);
+            }
+            (void)trg_release_workspace(b->s[i]);   // bounded memory: one workspace per worker
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int w = 1; w < b->workers; ++w) pool.emplace_back(work);
+    work();
+    for (auto &t : pool) t.join();
+    b->err.clear();
+    for (int i = 0; i < n; ++i)
+        if (!errs[i].empty()) {
+            b->err = "instance " + std::to_string(i) + ": " + errs[i];
+            break;
+        }
+    return first_rc.load();
+}
+}  // namespace
 
 extern "C" {
 
@@ -76,43 +159,10 @@ int trg_batch_create(int n, const double *betas, const double *hs, const int *Ds
     return TRG_OK;
 }
 
-int trg_batch_run(trg_batch *b, int nsteps, const int *axes) {
-    if (!b || nsteps < 0) return TRG_E_INVALID;
-    if (axes)
-        for (int i = 0; i < nsteps; ++i)
-            if (axes[i] < 0 || axes[i] > 3) return TRG_E_INVALID;
-    const int n = (int)b->s.size();
-    std::atomic<int> next{0};
-    std::atomic<int> first_rc{TRG_OK};
-    std::vector<std::string> errs(n);
-    auto work = [&]() {
-        (void)hipSetDevice(b->device);
-        for (int i = next++; i < n; i = next++) {
-            for (int k = 0; k < nsteps; ++k) {
-                const int ax = axes ? axes[k] : k % 4;
-                const int rc = triad_atrg_step(b->s[i], ax);
-                if (rc != TRG_OK) {
-                    errs[i] = trg_last_error(b->s[i]);
-                    int expect = TRG_OK;
-                    first_rc.compare_exchange_strong(expect, rc);
-                    break;
-                }
-            }
-            (void)trg_release_workspace(b->s[i]);   // bounded memory: one workspace per worker
-        }
-    };
-    std::vector<std::thread> pool;
-    for (int w = 1; w < b->workers; ++w) pool.emplace_back(work);
-    work();
-    for (auto &t : pool) t.join();
-    b->err.clear();
-    for (int i = 0; i < n; ++i)
-        if (!errs[i].empty()) {
-            b->err = "instance " + std::to_string(i) + ": " + errs[i];
-            break;
-        }
-    return first_rc.load();
-}
+
+int trg_batch_run(trg_batch *b, int nsteps, const int *axes) { return run_all(b, nsteps, axes, false); }
+
+int trg_batch_run_graphs(trg_batch *b, int nsteps, const int *axes) { return run_all(b, nsteps, axes, true); }
 
 int trg_batch_log_z(trg_batch *b, double *out_n) {
     if (!b || !out_n) return TRG_E_INVALID;

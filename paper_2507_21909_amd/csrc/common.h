@@ -135,8 +135,8 @@ struct JacobiBatch {
 };
 // Device-driven convergence (graph capture): the solver enqueues `sweeps`
 // sweeps and reads nothing back; once a sweep makes no rotation the remaining
-// launches return at once.  Non-finite pairs, or rotations still made in the
-// last sweep, set *status = code.
+// launches return at once.  Rotations still made in the last sweep set
+// *status = code, non-finite pairs *status = code + 2.
 struct DevLoop {
     int sweeps;
     int *status;

@@ -481,9 +481,9 @@ __global__ void sweep_begin_kernel(int *flags, int count) {
     for (int i = threadIdx.x; i < 2 * count; i += blockDim.x) flags[i] = 0;
 }
 
-// end of a device-driven sweep: the solve is done once no matrix rotated; a
-// non-finite pair, or rotations left after the last allowed sweep, set
-// *status = code
+// end of a device-driven sweep: the solve is done once no matrix rotated;
+// rotations left after the last allowed sweep set *status = code, a
+// non-finite pair *status = code + 2
 __global__ void sweep_end_kernel(int *flags, int count, int last, int *status, int code) {
     if (threadIdx.x || flags[2 * count]) return;
     int any = 0, bad = 0;
@@ -491,15 +491,18 @@ __global__ void sweep_end_kernel(int *flags, int count, int last, int *status, i
         any |= flags[i] != 0;
         bad |= flags[count + i] != 0;
     }
-    if (bad || (any && last)) *status = code;
+    if (bad) *status = code + 2;
+    else if (any && last) *status = code;
     if (bad || !any || last) flags[2 * count] = 1;
 }
 
 // the one-launch solver's verdict, device side: flags[i] < 0 is no convergence
 __global__ void full_check_kernel(const int *flags, int count, int *status, int code) {
     if (threadIdx.x) return;
-    for (int i = 0; i < count; ++i)
-        if (flags[i] < 0 || flags[count + i] != 0) *status = code;
+    for (int i = 0; i < count; ++i) {
+        if (flags[count + i] != 0) *status = code + 2;
+        else if (flags[i] < 0) *status = code;
+    }
 }
 }  // namespace
 

@@ -13,6 +13,7 @@
 // get the sign convention of the weight w(multi-index).
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -41,9 +42,14 @@ struct trg_state {
                                // [8..] kept counts
     std::vector<double> sigma_last;    // bond-swap singular values of the last step
     std::vector<double> resplit_last;  // re-split singular values / c_k of the last step
-    // the same two spectra on the device ([0, 1024) sigma, [1024, 2048) re-split);
-    // after a graph launch the host copies are refreshed from here on demand
+    // the same two spectra on the device ([0, 1024) sigma, [1024, 2048) re-split,
+    // [2048, 4096) their values before the step); after a graph launch the host
+    // copies are refreshed from here on demand
     double *dspec = nullptr;
+    // a recorded step's copy of the state it starts from (phi, psi, then the
+    // tangents' pairs; cap_state each), for the rollback of a checked replay
+    double *bak = nullptr;
+    size_t bak_cap = 0;
     bool spec_stale = false;
     size_t nsig = 0, nrsv = 0;
     // graph capture: most sweeps an eager step's iterative solve took, keyed by
@@ -268,6 +274,9 @@ int run_jacobi(Ctx &c, const JacobiBatch &jb, int ms, int *flags, double *work) 
                     "graph capture: no eager step of this method at these shapes has run on the state");
         cap = std::min(ms, it->second + it->second / 2 + 4);
     }
+    const char *env = getenv("TRG_GRAPH_SWEEP_CAP");   // test hook: a smaller cap for recorded solves
+    const int forced = env && *env ? atoi(env) : 0;
+    if (forced > 0 && jb.n > 96) cap = std::min(cap, forced);
     DevLoop dl{cap, c.dstatus, 3};
     return jacobi_svd(jb, ms, flags, work, c.st, &dl);
 }
@@ -1123,14 +1132,29 @@ void check_status(int status) {
                 "a truncation cut falls in a multiplet of more than 16 values (canonical basis not formed); "
                 "change tau_deg or D");
     TRG_REQUIRE(status != 3, TRG_E_NUMERICAL,
-                "Jacobi SVD of a replayed step: non-finite entries, or not converged within the sweeps "
-                "allowed at capture");
+                "Jacobi SVD of a replayed step not converged within the sweeps allowed at capture");
+    TRG_REQUIRE(status != 5, TRG_E_NUMERICAL, "Jacobi SVD of a replayed step met non-finite entries");
     TRG_REQUIRE(status != 4, TRG_E_NUMERICAL, "pivoted Cholesky of a replayed step met a non-finite pivot");
     TRG_REQUIRE(status == 0, TRG_E_NUMERICAL, "numerical status flag set");
 }
 
 __global__ void step_inc_kernel(int *k) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *k += 1;
+}
+
+__global__ void step_begin_kernel(double *dscal, int *dint) {
+    if (threadIdx.x || blockIdx.x) return;
+    dscal[3] = dscal[0];
+    dint[1] = dint[0];
+    dint[3] = dint[2];
+}
+
+// a failed step's rollback of the device scalars (accumulator, status, step index)
+__global__ void step_undo_kernel(double *dscal, int *dint) {
+    if (threadIdx.x || blockIdx.x) return;
+    dscal[0] = dscal[3];
+    dint[0] = dint[1];
+    dint[2] = dint[3];
 }
 
 // ---------------------------------------------------------------- one step
@@ -1143,9 +1167,24 @@ void do_step(trg_state *S, int axis, bool triad) {
                 "impurity tangents are carried by triad_atrg_step only (atrg_step: create the state without tangents)");
     S->ar.reset();
     Step T(S);
-    // accumulator and status before the step (dscal[3], dint[1]); restored if the step fails
-    copy(S->dscal + 3, S->dscal, 1, S->st);
-    TRG_HIP_CHECK(hipMemcpyAsync(S->dint + 1, S->dint, sizeof(int), hipMemcpyDeviceToDevice, S->st));
+    // accumulator, status and step index before the step (dscal[3], dint[1], dint[3]);
+    // restored if the step fails
+    hipLaunchKernelGGL(step_begin_kernel, dim3(1), dim3(1), 0, S->st, S->dscal, S->dint);
+    TRG_HIP_CHECK(hipGetLastError());
+    if (T.c.capture) {
+        // a recorded step also keeps the state and spectra it starts from
+        long n = S->chi;
+        for (int v : S->dims) n *= v;
+        TRG_REQUIRE(S->bak && S->bak_cap >= (size_t)(2 + 2 * S->ntan) * S->cap_state, TRG_E_STATE,
+                    "graph capture: no backup buffer");
+        copy(S->bak, S->phi, n, S->st);
+        copy(S->bak + S->cap_state, S->psi, n, S->st);
+        for (int t = 0; t < S->ntan; ++t) {
+            copy(S->bak + (2 + 2 * t) * S->cap_state, S->dphi[t], n, S->st);
+            copy(S->bak + (3 + 2 * t) * S->cap_state, S->dpsi[t], n, S->st);
+        }
+        copy(S->dspec + 2048, S->dspec, 2048, S->st);
+    }
     std::vector<int> order(d);
     for (int i = 0; i < d; ++i) order[i] = (axis + i) % d;
     Split sp = resplit(T, order);
@@ -1275,7 +1314,7 @@ int trg_create(const trg_options *opt, trg_state **out) {
         s->ar.set_cap(opt->workspace_cap);
         TRG_HIP_CHECK(hipMalloc(&s->dscal, 2048 * sizeof(double)));
         TRG_HIP_CHECK(hipMalloc(&s->dint, 256 * sizeof(int)));
-        TRG_HIP_CHECK(hipMalloc(&s->dspec, 2048 * sizeof(double)));
+        TRG_HIP_CHECK(hipMalloc(&s->dspec, 4096 * sizeof(double)));
     } catch (const Error &e) {
         g_err = e.what();
         trg_destroy(s);
@@ -1299,6 +1338,7 @@ int trg_destroy(trg_state *s) {
     if (s->dscal) (void)hipFree(s->dscal);
     if (s->dint) (void)hipFree(s->dint);
     if (s->dspec) (void)hipFree(s->dspec);
+    if (s->bak) (void)hipFree(s->bak);
     delete s;
     return TRG_OK;
 }
@@ -1500,6 +1540,7 @@ struct trg_graph {
     std::vector<int> dims_in, dims_out;
     int chi_in = 0, chi_out = 0;
     size_t nsig = 0, nrsv = 0;
+    long nstate = 0;   // elements of phi (and psi) when the step starts
 };
 
 int trg_graph_destroy(trg_graph *g) {
@@ -1537,6 +1578,19 @@ int trg_graph_capture(trg_state *s, int method, int axis, trg_graph **out) {
     try {
         DevGuard dg(s->opt.device);
         TRG_HIP_CHECK(hipStreamSynchronize(user));
+        g->nstate = s->chi;
+        for (int v : s->dims) g->nstate *= v;
+        const size_t need = (size_t)(2 + 2 * s->ntan) * s->cap_state;
+        if (s->bak_cap < need) {
+            if (s->bak) (void)hipFree(s->bak);
+            s->bak = nullptr;
+            s->bak_cap = 0;
+            if (hipMalloc(&s->bak, need * sizeof(double)) != hipSuccess) {
+                (void)hipGetLastError();
+                throw Error(TRG_E_NOMEM, "graph capture: backup of the state could not be allocated");
+            }
+            s->bak_cap = need;
+        }
         TRG_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         s->st = cs;
         s->capture_on = true;
@@ -1575,7 +1629,7 @@ int trg_graph_capture(trg_state *s, int method, int axis, trg_graph **out) {
     return TRG_OK;
 }
 
-int trg_graph_launch(trg_graph *g) {
+int trg_graph_launch(trg_graph *g, int check) {
     if (!g || !g->s || !g->exec) return TRG_E_INVALID;
     trg_state *s = g->s;
     if (!s->init || s->gen != g->gen) {
@@ -1590,10 +1644,35 @@ int trg_graph_launch(trg_graph *g) {
         s->err = "step index past the sketch counter's 16 bits";
         return TRG_E_UNSUPPORTED;
     }
+    const size_t nsig0 = s->nsig, nrsv0 = s->nrsv;
+    const bool stale0 = s->spec_stale;
     try {
         DevGuard dg(s->opt.device);
         TRG_HIP_CHECK(hipGraphLaunch(g->exec, s->st));
+        if (check) {
+            int status = 0;
+            TRG_HIP_CHECK(hipMemcpyAsync(&status, s->dint, sizeof(int), hipMemcpyDeviceToHost, s->st));
+            TRG_HIP_CHECK(hipStreamSynchronize(s->st));
+            if (status != 0) {
+                // back to the state the step started from (it kept a copy)
+                const size_t n = (size_t)g->nstate;
+                trg::copy(s->phi, s->bak, n, s->st);
+                trg::copy(s->psi, s->bak + s->cap_state, n, s->st);
+                for (int t = 0; t < s->ntan; ++t) {
+                    trg::copy(s->dphi[t], s->bak + (2 + 2 * t) * s->cap_state, n, s->st);
+                    trg::copy(s->dpsi[t], s->bak + (3 + 2 * t) * s->cap_state, n, s->st);
+                }
+                trg::copy(s->dspec, s->dspec + 2048, 2048, s->st);
+                hipLaunchKernelGGL(trg::step_undo_kernel, dim3(1), dim3(1), 0, s->st, s->dscal, s->dint);
+                TRG_HIP_CHECK(hipGetLastError());
+                TRG_HIP_CHECK(hipStreamSynchronize(s->st));
+                trg::check_status(status);
+            }
+        }
     } catch (const Error &e) {
+        s->nsig = nsig0;
+        s->nrsv = nrsv0;
+        s->spec_stale = stale0;
         return fail(s, e);
     }
     s->k += 1;

@@ -43,6 +43,49 @@ def test_batch_equals_sequential_bitwise():
     assert np.array_equal(got, np.array(ref))
 
 
+def test_batch_graphs_equal_eager_bitwise():
+    """trg_batch_run_graphs replays the steady steps from graphs: same bits as the eager batch."""
+    betas = [0.140, 0.1497, 0.160, 0.1497, 0.150, 0.145, 0.1497, 0.155]
+    hs = [0.0, 1e-4, 0.0, 1e-3, 1e-2, 0.0, 1e-4, 1e-3]
+    Ds = [8, 12, 16, 24, 12, 4, 8, 16]
+    nsteps = 16
+    _say("graph batch of", len(betas))
+    b = trg.Batch(betas, hs, Ds, seed=SEED)
+    t0 = time.perf_counter()
+    b.run(nsteps)
+    ref = b.log_z_per_site()
+    t_eager = time.perf_counter() - t0
+    b.close()
+    g = trg.Batch(betas, hs, Ds, seed=SEED)
+    t0 = time.perf_counter()
+    g.run(nsteps, graphs=True)
+    got = g.log_z_per_site()
+    t_graph = time.perf_counter() - t0
+    _say("eager %.3f s, graphs %.3f s" % (t_eager, t_graph))
+    assert np.array_equal(got, ref)
+    # a second run continues the flows: the graphs of the first run were retired with it
+    g.run(4, axes=[1, 2, 3, 0], graphs=True)
+    b2 = trg.Batch(betas, hs, Ds, seed=SEED)
+    b2.run(nsteps)
+    b2.run(4, axes=[1, 2, 3, 0])
+    assert np.array_equal(g.log_z_per_site(), b2.log_z_per_site())
+
+
+def test_batch_graphs_fall_back_to_eager(monkeypatch):
+    """Replays that exceed their recorded sweeps are rolled back and taken eagerly: same bits."""
+    betas, hs, Ds = [0.1497, 0.160, 0.150], [1e-4, 0.0, 1e-3], [12, 16, 12]
+    nsteps = 10
+    _say("graph batch fallback")
+    b = trg.Batch(betas, hs, Ds, seed=SEED)
+    b.run(nsteps)
+    ref = b.log_z_per_site()
+    monkeypatch.setenv("TRG_GRAPH_SWEEP_CAP", "2")
+    g = trg.Batch(betas, hs, Ds, seed=SEED)
+    g.run(nsteps, graphs=True)
+    monkeypatch.delenv("TRG_GRAPH_SWEEP_CAP")
+    assert np.array_equal(g.log_z_per_site(), ref)
+
+
 def test_batch_custom_axes_and_errors():
     b = trg.Batch([0.0, 0.0], [0.3, 0.0], [4, 6], seed=SEED)
     b.run(6, axes=[3, 2, 1, 0, 3, 2])

@@ -106,6 +106,60 @@ def test_graph_launches_back_to_back():
     assert np.array_equal(s.export(trg.T_PHI), eager.export(trg.T_PHI))
 
 
+def _steady(s, D):
+    k = 0
+    while True:
+        before = s.shape()[:2]
+        s.triad_atrg_step(k % 4)
+        k += 1
+        if s.shape()[:2] == before:
+            return k
+
+
+def test_graph_checked_replay_rolls_back(monkeypatch):
+    """A replay whose Jacobi solve needs more sweeps than recorded fails and, checked, leaves the state as it was.
+
+    TRG_GRAPH_SWEEP_CAP=1 records the panel solves with one sweep (a host-side
+    cap: every launch still exits normally), which no solve meets.
+    """
+    _say("graph checked rollback")
+    D = 12   # triad Grams of 144 x 144: the panel solver
+    ref = trg.Solver(seed=7)
+    ref.tensor_init(trg.MODEL_ISING, 0.1497, 1e-4, D)
+    s = trg.Solver(seed=7)
+    s.tensor_init(trg.MODEL_ISING, 0.1497, 1e-4, D)
+    k = _steady(s, D)
+    for i in range(k):
+        ref.triad_atrg_step(i % 4)
+    monkeypatch.setenv("TRG_GRAPH_SWEEP_CAP", "1")
+    g = s.capture(k % 4)
+    monkeypatch.delenv("TRG_GRAPH_SWEEP_CAP")
+    lz, phi = s.log_z_per_site(), s.export(trg.T_PHI)
+    sig = s.export(trg.T_SIGMA)
+    with pytest.raises(trg.TrgError) as ei:
+        g.launch(check=True)
+    assert ei.value.code == -4 and "sweeps allowed at capture" in str(ei.value)
+    assert s.shape()[2] == k
+    assert s.log_z_per_site() == lz
+    assert np.array_equal(s.export(trg.T_PHI), phi)
+    assert np.array_equal(s.export(trg.T_SIGMA), sig)
+    # the step taken eagerly after the rollback is the reference's step
+    s.triad_atrg_step(k % 4)
+    ref.triad_atrg_step(k % 4)
+    assert s.log_z_per_site() == ref.log_z_per_site()
+    assert np.array_equal(s.export(trg.T_PSI), ref.export(trg.T_PSI))
+    # unchecked, the failure surfaces at the next status read, without rollback
+    monkeypatch.setenv("TRG_GRAPH_SWEEP_CAP", "1")
+    g2 = s.capture((k + 1) % 4)
+    monkeypatch.delenv("TRG_GRAPH_SWEEP_CAP")
+    g2.launch()
+    with pytest.raises(trg.TrgError) as ei:
+        s.log_z_per_site()
+    assert ei.value.code == -4
+    g.close()
+    g2.close()
+
+
 def test_graph_state_rules():
     """Capture needs an eager step at the current shapes; tensor_init and workspace release retire graphs."""
     _say("graph state rules")
