@@ -58,6 +58,7 @@ def cpu_baseline(D, r, beta, h, seed):
     scale = step_flops(D) / step_flops(d0)
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
     return {"value": 1.0 / (t_step * scale), "unit": "RG steps/s", "cores": int(threads), "kind": "oracle",
+            "extrapolated": True, "measured_steps_per_s_at_D16": 1.0 / t_step,
             "sample": "one steady-state oracle step (the 5th) of the same flow at D=16, R=%d: %.1f s on %s host "
                       "threads, scaled to D=%d by the step's algorithmic flop ratio %.1f" % (
                           r * d0, t_step, threads, D, scale)}
@@ -181,7 +182,7 @@ def derivative_main(args):
         s.close()
         return f, d, t
 
-    for j in range(args.derivative_points):
+    for j in range(args.derivative_first, args.derivative_first + args.derivative_points):
         beta = 0.148 + 0.003 * j / 15
         f, (db, dh), t_tan = flow(beta, h, trg.TAN_BETA | trg.TAN_H)
         _, _, t_plain = flow(beta, h, 0)
@@ -221,6 +222,8 @@ def main():
     ap.add_argument("--derivatives", action="store_true",
                     help="internal energy / magnetisation scan by the impurity tangents (use --D 24)")
     ap.add_argument("--derivative-points", type=int, default=16)
+    ap.add_argument("--derivative-first", type=int, default=0,
+                    help="first beta index j of the scan (beta_j = 0.148 + 0.003 j / 15)")
     ap.add_argument("--graphs", action="store_true",
                     help="time steps replayed from HIP graphs recorded after the warmup (no kernel timing)")
     args = ap.parse_args()

@@ -183,8 +183,8 @@ int trg_release_workspace(trg_state *s);
  * last tensor_init: that step sized the workspace (nothing may be allocated
  * while recording) and logged how many sweeps each Jacobi solve needed.
  * Otherwise TRG_E_STATE, and the state is unchanged.  The recorded step
- * reads nothing back: the panel Jacobi solves run at most 1.5 times the most
- * sweeps logged for them plus 4, stopping early on device flags, and
+ * reads nothing back: the panel Jacobi solves run at most twice the most
+ * sweeps logged for them plus 8, stopping early on device flags, and
  * numerical failures set the state's device status flag.  Neither an
  * n > 1024 squeezer Gram nor the eigensolver fallback can be recorded
  * (TRG_E_UNSUPPORTED).

@@ -254,9 +254,10 @@ void col_slice(Ctx &c, const double *src, long rows, long cols, int k, double *d
 // One-sided Jacobi under the step's convergence policy.  Eager: the host reads
 // every sweep's rotation count and the sweeps used are logged for the solve
 // (its call order in the step and its shape).  Captured: nothing is read back;
-// the panel solver runs device-driven up to 1.5 times the most sweeps logged
-// for the same solve, plus 4 (status 3 if that is not enough), the one-launch
-// solver up to max_sweeps as eagerly.
+// the panel solver runs device-driven up to twice the most sweeps logged for
+// the same solve, plus 8 (status 3 if that is not enough: a squeezer solve can
+// take 10 sweeps in one step and 40 a few steps later), the one-launch solver
+// up to max_sweeps as eagerly.
 int run_jacobi(Ctx &c, const JacobiBatch &jb, int ms, int *flags, double *work) {
     const std::array<int, 4> key{c.solve_idx++, jb.count, jb.m, jb.n};
     if (!c.capture) {
@@ -272,7 +273,7 @@ int run_jacobi(Ctx &c, const JacobiBatch &jb, int ms, int *flags, double *work) 
         auto it = c.sweep_log ? c.sweep_log->find(key) : std::map<std::array<int, 4>, int>::iterator();
         TRG_REQUIRE(c.sweep_log && it != c.sweep_log->end(), TRG_E_STATE,
                     "graph capture: no eager step of this method at these shapes has run on the state");
-        cap = std::min(ms, it->second + it->second / 2 + 4);
+        cap = std::min(ms, 2 * it->second + 8);
     }
     const char *env = getenv("TRG_GRAPH_SWEEP_CAP");   // test hook: a smaller cap for recorded solves
     const int forced = env && *env ? atoi(env) : 0;

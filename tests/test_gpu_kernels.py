@@ -33,7 +33,8 @@ def test_gemm_f64(shape, ta, tb):
     assert np.max(np.abs(c - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))) * np.sqrt(k)
 
 
-@pytest.mark.parametrize("m,n", [(4, 4), (37, 5), (256, 64), (1000, 33), (5000, 64), (70000, 17), (300000, 2)])
+@pytest.mark.parametrize("m,n", [(4, 4), (37, 5), (256, 64), (1000, 33), (5000, 64), (70000, 17), (300000, 2),
+                                 (64, 64), (257, 40), (100003, 64)])
 def test_tsqr(m, n):
     _say("tsqr", m, n)
     rng = np.random.default_rng(m + n)
@@ -55,6 +56,14 @@ def test_tsqr_rank_deficient():
     q, r = trg.selftest_tsqr(a)
     assert np.max(np.abs(q @ r - a)) < 1e-12 * np.max(np.abs(a))
     assert np.max(np.abs(q.T @ q - np.eye(12))) < 1e-12
+    # 64 columns: rank 20 with zero and repeated columns (column-per-lane blocks)
+    a = rng.standard_normal((9000, 20)) @ rng.standard_normal((20, 64))
+    a[:, 7] = 0.0
+    a[:, 40] = a[:, 2]
+    q, r = trg.selftest_tsqr(a)
+    assert np.max(np.abs(q @ r - a)) < 1e-12 * np.max(np.abs(a))
+    assert np.max(np.abs(q.T @ q - np.eye(64))) < 1e-12
+    assert np.all(np.diagonal(r) >= 0)
 
 
 # wide QR (n > 64): blocked Householder over 64-column TSQR panels; ragged
