@@ -108,3 +108,9 @@ def test_grid_fp64_against_oracle(beta, h):
     name = "grid_d16_b%.4f_h%g" % (beta, h)
     _say("grid", name)
     run_against(_golden(name))
+
+
+def test_d32_field_fp64_against_oracle():
+    """D = 32 (R = 224) with h = 1e-4, 12 steps: log Z/V and the per-step spectra of the oracle's flow."""
+    _say("d32 h=1e-4")
+    run_against(_golden("triad_d32_h1e-4_12steps"), spectra_steps=12)
