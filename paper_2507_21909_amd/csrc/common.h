@@ -5,6 +5,8 @@
 #include <cstddef>
 #include <cstdint>
 #include <stdexcept>
+#include <array>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -48,7 +50,18 @@ struct GemmArgs {
     // which writes C directly in a layout that interleaves the row and column
     // legs; 0 keeps r * sCr (c * sCn)
     int cR2, cN2; long sCr2, sCn2;
+    // tile rows per L2 group of the tile walk (0: the default, 8); any value
+    // gives the same bits (it only reorders which workgroup takes which tile)
+    int gm;
 };
+// Tile-walk autotuning (gemm.hip).  The first eager launch of a large shape
+// with beta = 0 (a rerun writes the same C) runs once per candidate group size
+// {4, 8, 16}, timed with events on its stream, and the fastest is kept for the
+// key (kernel variant and shape); later launches, launches being recorded into
+// a graph and small shapes take the cached or default value.  The group size
+// only reorders tiles over workgroups, so every choice gives the same bits.
+// TRG_AUTOTUNE=0 switches tuning off, TRG_GEMM_GM=g forces g.
+int tuned_gm(const std::array<long, 8> &key, hipStream_t st, bool eligible, const std::function<void(int)> &launch);
 // ev0 / ev1 (optional): events stamped at the kernel's start and end
 void gemm(const GemmArgs &g, Prec prec, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void gemm_f64(const GemmArgs &g, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
@@ -110,6 +123,7 @@ struct PlaneGemm {
     int cR2, cN2;
     long sCr2, sCn2;
     double alpha, beta;
+    int gm;   // tile rows per L2 group (0: 8); bit-neutral, as GemmArgs::gm
 };
 size_t bf16_planes_elems(long rows, long Kp, int batch);
 // src[b][r][k] at src + b sB + r sR + k sK (rows x K, batch entries) -> planes in dst

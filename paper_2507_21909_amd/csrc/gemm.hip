@@ -11,6 +11,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 
 #include <hip/hip_ext.h>
 
@@ -77,12 +79,13 @@ __device__ inline long c_off(const GemmArgs &g, int r, int c) {
     return ro + co;
 }
 
-__device__ inline void tile_of(int &mt, int &nt) {
+__device__ inline void tile_of(int &mt, int &nt, int gm) {
+    const int G = gm > 0 ? gm : GM;
     const int nx = gridDim.x, ny = gridDim.y, T = nx * ny;
     const int h = blockIdx.y * nx + blockIdx.x;
     const int L = (T % 8 == 0) ? (h % 8) * (T / 8) + h / 8 : h;
-    const int in_group = GM * nx, first = (L / in_group) * GM;
-    const int gs = min(ny - first, GM);
+    const int in_group = G * nx, first = (L / in_group) * G;
+    const int gs = min(ny - first, G);
     mt = first + (L % in_group) % gs;
     nt = (L % in_group) / gs;
 }
@@ -96,7 +99,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
     double *C;
     batch_ptrs(g, A, B, C);
     int mt, nt;
-    tile_of(mt, nt);
+    tile_of(mt, nt, g.gm);
     const int m0 = mt * TM, n0 = nt * TM;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_vec_kernel(GemmArgs g) {
     double *C;
     batch_ptrs(g, A, B, C);
     int mt, nt;
-    tile_of(mt, nt);
+    tile_of(mt, nt, g.gm);
     const int m0 = mt * TM, n0 = nt * TM;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
@@ -325,7 +328,56 @@ void launch_vec(bool ak1, bool bn1, dim3 grid, hipStream_t st, hipEvent_t ev0, h
     if (ev0) hipExtLaunchKernelGGL(kern, grid, dim3(NT), 0, st, ev0, ev1, 0, h);
     else hipLaunchKernelGGL(kern, grid, dim3(NT), 0, st, h);
 }
+std::mutex tune_mu;
+std::map<std::array<long, 8>, int> tune_cache;
+
+int env_int(const char *name, int dflt) {
+    const char *e = getenv(name);
+    return e && *e ? atoi(e) : dflt;
+}
 }  // namespace
+
+int tuned_gm(const std::array<long, 8> &key, hipStream_t st, bool eligible, const std::function<void(int)> &launch) {
+    static const int forced = env_int("TRG_GEMM_GM", 0);
+    static const bool on = env_int("TRG_AUTOTUNE", 1) != 0;
+    static const bool trace = env_int("TRG_GEMM_TRACE", 0) != 0;
+    if (forced > 0) return forced;
+    {
+        std::lock_guard<std::mutex> lk(tune_mu);
+        auto it = tune_cache.find(key);
+        if (it != tune_cache.end()) return it->second;
+    }
+    if (!on || !eligible) return 0;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    TRG_HIP_CHECK(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return 0;
+    const int cand[3] = {4, 8, 16};
+    hipEvent_t ev[4];
+    for (auto &e : ev) TRG_HIP_CHECK(hipEventCreate(&e));
+    TRG_HIP_CHECK(hipEventRecord(ev[0], st));
+    for (int i = 0; i < 3; ++i) {
+        launch(cand[i]);
+        TRG_HIP_CHECK(hipEventRecord(ev[i + 1], st));
+    }
+    TRG_HIP_CHECK(hipEventSynchronize(ev[3]));
+    int best = 0;
+    float best_ms = 0.0f;
+    for (int i = 0; i < 3; ++i) {
+        float ms = 0.0f;
+        TRG_HIP_CHECK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+        if (i == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = cand[i];
+        }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (trace)
+        fprintf(stderr, "[tune] kind %ld M %ld N %ld K %ld batch %ld inner %ld: group %d (%.3f ms)\n", key[0], key[1],
+                key[2], key[3], key[4], key[5], best, best_ms);
+    std::lock_guard<std::mutex> lk(tune_mu);
+    tune_cache[key] = best;
+    return best;
+}
 
 void gemm_f64(const GemmArgs &g, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
@@ -354,6 +406,16 @@ void gemm_f64(const GemmArgs &g, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
         dim3 grid(cdiv(h.N, tm), cdiv(h.M, tm), h.batch * inner);
         bool ak1 = false, bn1 = false;
         if (!big && vec_ok(h, &ak1, &bn1)) {
+            if (h.gm == 0) {
+                const double fl = 2.0 * h.M * (double)h.N * (double)h.K * h.batch;
+                const std::array<long, 8> key{(long)(ak1 ? 2 : 0) + (bn1 ? 1 : 0), h.M, h.N, (long)h.K, h.batch, inner,
+                                              h.cR2 > 0 || h.cN2 > 0, 0};
+                h.gm = tuned_gm(key, st, h.beta == 0.0 && fl >= 2e10, [&](int gm) {
+                    GemmArgs x = h;
+                    x.gm = gm;
+                    launch_vec<0>(ak1, bn1, grid, st, nullptr, nullptr, x);
+                });
+            }
             if (ev0 && (long)g.batch * inner <= 65535) launch_vec<1>(ak1, bn1, grid, st, ev0, ev1, h);
             else launch_vec<0>(ak1, bn1, grid, st, nullptr, nullptr, h);
             continue;

@@ -97,12 +97,13 @@ __device__ inline long pc_off(const PlaneGemm &g, int r, int c) {
     return ro + co;
 }
 
-__device__ inline void ptile_of(int &mt, int &nt) {
+__device__ inline void ptile_of(int &mt, int &nt, int gm) {
+    const int G = gm > 0 ? gm : PGM;
     const int nx = gridDim.x, ny = gridDim.y, T = nx * ny;
     const int h = blockIdx.y * nx + blockIdx.x;
     const int L = (T % 8 == 0) ? (h % 8) * (T / 8) + h / 8 : h;
-    const int in_group = PGM * nx, first = (L / in_group) * PGM;
-    const int gs = min(ny - first, PGM);
+    const int in_group = G * nx, first = (L / in_group) * G;
+    const int gs = min(ny - first, G);
     mt = first + (L % in_group) % gs;
     nt = (L % in_group) / gs;
 }
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(PNT) void gemm_planes_kernel(PlaneGemm g) {
     double *C = g.C + (long)bo * g.sCb + (long)bi * g.sCi;
     const int kbeg = bi * g.kslice, kend = min(g.Kp, kbeg + g.kslice);
     int mt, nt;
-    ptile_of(mt, nt);
+    ptile_of(mt, nt, g.gm);
     const int m0 = mt * PT, n0 = nt * PT;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
@@ -245,8 +246,18 @@ void gemm_planes(const PlaneGemm &g, hipStream_t st, hipEvent_t ev0, hipEvent_t 
                     (long)g.inner * g.kslice >= g.Kp && (long)g.batch * g.inner <= 65535,
                 -6, "gemm_planes: bad K slicing");
     dim3 grid(cdiv(g.N, PT), cdiv(g.M, PT), g.batch * g.inner);
-    if (ev0) hipExtLaunchKernelGGL(gemm_planes_kernel<1>, grid, dim3(PNT), 0, st, ev0, ev1, 0, g);
-    else hipLaunchKernelGGL(gemm_planes_kernel<0>, grid, dim3(PNT), 0, st, g);
+    PlaneGemm h = g;
+    if (h.gm == 0) {
+        const double fl = 6.0 * 2.0 * h.M * (double)h.N * (double)h.Kp * h.batch;
+        const std::array<long, 8> key{10, h.M, h.N, (long)h.Kp, h.batch, h.inner, h.kslice, h.cR2 > 0 || h.cN2 > 0};
+        h.gm = tuned_gm(key, st, h.beta == 0.0 && fl >= 2e10, [&](int gm) {
+            PlaneGemm x = h;
+            x.gm = gm;
+            hipLaunchKernelGGL(gemm_planes_kernel<0>, grid, dim3(PNT), 0, st, x);
+        });
+    }
+    if (ev0) hipExtLaunchKernelGGL(gemm_planes_kernel<1>, grid, dim3(PNT), 0, st, ev0, ev1, 0, h);
+    else hipLaunchKernelGGL(gemm_planes_kernel<0>, grid, dim3(PNT), 0, st, h);
     TRG_HIP_CHECK(hipGetLastError());
 }
 
