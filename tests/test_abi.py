@@ -56,3 +56,17 @@ def test_binding_loads_and_rejects_bad_arguments(lib_path):
     assert lib.atrg_step(None, 0) == -1
     out = ctypes.c_double()
     assert lib.log_z_per_site(None, ctypes.byref(out)) == -1
+
+
+def test_graph_and_batch_entry_points_reject_bad_arguments(lib_path):
+    import ctypes
+    from paper_2507_21909_amd import binding
+    lib = binding.load_library(lib_path)
+    g = ctypes.c_void_p()
+    assert lib.trg_graph_capture(None, 1, 0, ctypes.byref(g)) == -1
+    assert lib.trg_graph_launch(None, 0) == -1
+    assert lib.trg_graph_launch(None, 1) == -1
+    assert lib.trg_graph_destroy(None) == 0
+    assert lib.trg_batch_run_graphs(None, 4, None) == -1
+    assert lib.trg_batch_run(None, 4, None) == -1
+    assert lib.trg_strerror(-7).decode().startswith("truncation cut inside a multiplet")
