@@ -30,8 +30,18 @@ Readings (the paper gives no formulas for this part):
   truncated SVD when the discarded values are negligible), and split over
   both factors: d(X sigma) = dM Y, dY = (1 - Y Y^T) dM^T X sigma^+ with
   dM = dB C + B dC, so F = (X sigma) U^X and G = Y U^Y both move;
-* the triad isometries and squeezers are held; E..H take dA, d(X sigma), dY,
-  dD.
+* triad isometries: the coarse tensor depends on each U only through its
+  projector U U^T (E = A U^A meets I = U^A in makeMG, and so on), so a
+  first-order change of U within its kept subspace cancels.  The kept
+  subspace moves with the Gram (eq. HOSVD): dU = W C, W the discarded
+  eigenvectors and C[j, i] = w_j^T dG u_i / (lam_i - lam_j) (first-order
+  perturbation of an invariant subspace), with dG the Gram's tangent from
+  dA, d(X sigma), dY, dD.  Holding U instead (iso=False) gives the
+  derivative of the flow with its isometries frozen, which near T_c differs
+  from the flow's own derivative by 10 % or more; the squeezers are held
+  (freezing them moves the derivative by about 1e-3 at D = 8);
+* E..H take dA, d(X sigma), dY, dD and A dU^A, (X sigma) dU^X, Y dU^Y, D dU^D,
+  and the triad tensors I..L in makeMG / makeMH take dU as well.
 """
 import math
 
@@ -134,8 +144,56 @@ def _bond_tangent(kp, db, dcc):
     return dxs.reshape(x.shape), dy.reshape(y.shape)
 
 
-def step(ist, axis, prm, method):
-    """One coarse-graining step of the pure state and of every tangent."""
+def _gram_tangents(a, x, sig, y, dt, da, dxs, dy, ddm):
+    """Tangents of the four triad Grams (see trg.triad_grams).
+
+    With M_k = X sigma Y^T the truncated bond-swap product, X sigma^2 X^T =
+    M_k M_k^T and Y sigma^2 Y^T = M_k^T M_k; along dM_k = d(X sigma) Y^T + X
+    sigma dY^T with Y^T dY = 0 they move by d(X sigma)(X sigma)^T + transpose
+    and by Y Wg Y^T + dY sigma^2 Y^T + transpose, Wg = (X sigma)^T d(X sigma) + transpose.
+    """
+    def sym(g):
+        return g + g.transpose(2, 3, 0, 1)
+    xs = x * sig
+    s2 = sig * sig
+    xsx = np.einsum("aijtg,bijtg->ab", xs, xs, optimize=True)
+    dxsx = np.einsum("aijtg,bijtg->ab", dxs, xs, optimize=True)
+    dxsx = dxsx + dxsx.T
+    wg = np.einsum("aijtg,aijth->gh", xs, dxs, optimize=True)
+    wg = wg + wg.T
+    ysy = np.einsum("aijtg,g,bijtg->ab", y, s2, y, optimize=True)
+    dysy = np.einsum("aijtg,g,bijtg->ab", dy, s2, y, optimize=True)
+    dysy = dysy + dysy.T + np.einsum("aijtg,gh,bijth->ab", y, wg, y, optimize=True)
+    dga = sym(np.einsum("xijta,ab,xkltb->ijkl", da, xsx, a, optimize=True)) + \
+        np.einsum("xijta,ab,xkltb->ijkl", a, dxsx, a, optimize=True)
+    dgx = sym(np.einsum("aijtg,akltg->ijkl", dxs, xs, optimize=True))
+    dgy = sym(np.einsum("aijtg,g,akltg->ijkl", dy, s2, y, optimize=True)) + \
+        np.einsum("aijtg,gh,aklth->ijkl", y, wg, y, optimize=True)
+    dgd = sym(np.einsum("xijta,ab,xkltb->ijkl", ddm, ysy, dt, optimize=True)) + \
+        np.einsum("xijta,ab,xkltb->ijkl", dt, dysy, dt, optimize=True)
+    nn = a.shape[1] * a.shape[2]
+    return [g.reshape(nn, nn) for g in (dga, dgx, dgy, dgd)]
+
+
+def _iso_tangent(gram, dgram, d1, d2, cap, prm):
+    """dU of a truncated HOSVD isometry (trg.triad_isometry) along dgram, [d1, d2, cap]."""
+    n = d1 * d2
+    if n <= cap:
+        return np.zeros((d1, d2, n))                 # identity: nothing truncated
+    lam, w = trg.jacobi_eigh(gram)
+    kept = trg.kept_count(lam, cap, prm.eps_lam, prm.tau_deg)
+    u, wd = w[:, :kept], w[:, kept:]
+    sg = trg.fix_signs(u, (d1, d2))
+    cm = (wd.T @ dgram @ u) / (lam[None, :kept] - lam[kept:, None])
+    out = np.zeros((n, cap))
+    out[:, :kept] = (wd @ cm) * sg
+    return out.reshape(d1, d2, cap)
+
+
+def step(ist, axis, prm, method, iso=True):
+    """One coarse-graining step of the pure state and of every tangent.
+
+    iso: differentiate the triad isometries (True) or hold them (False)."""
     kp = {}
     st = ist.pure
     d = st.d
@@ -159,6 +217,21 @@ def step(ist, axis, prm, method):
             dh = np.einsum("xijtb,ijk->xktb", ddm, tl, optimize=True)     # H = D U^D
             dphi_n = trg.make_phi(de, kp["f"], ti, tj, m1, m2, m3) + trg.make_phi(kp["e"], df, ti, tj, m1, m2, m3)
             dpsi_n = trg.make_psi(dg, kp["h"], tk, tl, n1, n2, n3) + trg.make_psi(kp["g"], dh, tk, tl, n1, n2, n3)
+            if iso:
+                a, x, sig, y, dt = kp["a"], kp["x"], kp["sig"], kp["y"], kp["dd"]
+                d1, d2, cap = ti.shape
+                grams = trg.triad_grams(a, x, sig, y, dt)
+                dgr = _gram_tangents(a, x, sig, y, dt, da, dxs, dy, ddm)
+                dti, dtj, dtk, dtl = (_iso_tangent(gm, dgm, d1, d2, cap, prm) for gm, dgm in zip(grams, dgr))
+                de2 = np.einsum("xijta,ijk->xkta", a, dti, optimize=True)
+                df2 = np.einsum("aijtg,ijk,g->aktg", x, dtj, sig, optimize=True)
+                dg2 = np.einsum("bijtg,ijk->bktg", y, dtk, optimize=True)
+                dh2 = np.einsum("xijtb,ijk->xktb", dt, dtl, optimize=True)
+                e, f, g, h = kp["e"], kp["f"], kp["g"], kp["h"]
+                dphi_n = dphi_n + trg.make_phi(de2, f, ti, tj, m1, m2, m3) + trg.make_phi(e, df2, ti, tj, m1, m2, m3) \
+                    + trg.make_phi(e, f, dti, tj, m1, m2, m3) + trg.make_phi(e, f, ti, dtj, m1, m2, m3)
+                dpsi_n = dpsi_n + trg.make_psi(dg2, h, tk, tl, n1, n2, n3) + trg.make_psi(g, dh2, tk, tl, n1, n2, n3) \
+                    + trg.make_psi(g, h, dtk, tl, n1, n2, n3) + trg.make_psi(g, h, tk, dtl, n1, n2, n3)
         else:
             dphi_n, dpsi_n = _atrg_tangent(kp, da, dxs, dy, ddm)
         new.append((np.ascontiguousarray(np.transpose(dphi_n, inv)),
@@ -200,8 +273,8 @@ def derivatives(ist):
     return out
 
 
-def run(beta, h, prm, nsteps, method="triad", d=4, wrt=("beta", "h")):
+def run(beta, h, prm, nsteps, method="triad", d=4, wrt=("beta", "h"), iso=True):
     ist = ImpurityState(beta, h, d, wrt)
     for i in range(nsteps):
-        step(ist, i % d, prm, method)
+        step(ist, i % d, prm, method, iso)
     return derivatives(ist), ist
