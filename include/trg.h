@@ -152,12 +152,14 @@ int gu_wen_x(trg_state *s, int axis, double *out);
 /*
  * impurity_derivatives -- d(log Z/V)/d(beta) and d(log Z/V)/dh of the torus the
  * state represents, by the impurity-tensor method (Sec. III D): the derivative
- * of the site tensor, summed over the sites, is carried through every step
- * with the pure flow's truncations (triad isometries, squeezers, norms) held,
+ * of the site tensor, summed over the sites, is carried through every step:
  * the re-split and bond-swap tangents taken in the tangent space of the
- * rank-chi matrices; then d(log Z/V) = 2^-n Tr dT^(n) / Tr T^(n).  Exact
- * where nothing is truncated; otherwise it differs from the derivative of
- * the truncated flow by terms of the order of the truncation.  The internal
+ * rank-chi matrices, the triad isometries' kept subspaces moved with their
+ * Grams (first-order invariant-subspace perturbation), the squeezers and
+ * norms held; then d(log Z/V) = 2^-n Tr dT^(n) / Tr T^(n).  Exact where
+ * nothing is truncated; otherwise it differs from the derivative of the
+ * truncated flow by what the held squeezers and the bond swap's tangent-space
+ * form leave out (about 4e-4 relative at D = 8 near T_c).  The internal
  * energy per site is u = -(*dbeta) and the magnetisation m = *dh.
  * The state must be created with opt.tangents; each output pointer (host,
  * may be NULL) receives its derivative, or NaN if that tangent is not

@@ -781,10 +781,27 @@ void atrg_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi) {
 
 // ---------------------------------------------------------------- triad-ATRG
 // triad isometries U[(t1, t2), k] of the four pair Grams (eq. HOSVD), one batch
-void triad_isos(Step &T, const DT *grams, int d1, int d2, int rcap, DT *U) {
+// what the impurity tangents need of the triad isometries: the Grams' full
+// eigenbases, the kept counts and the sign vectors of the kept columns
+struct IsoKeep {
+    bool truncated = false;
+    int n = 0, cap = 0, d1 = 0, d2 = 0;
+    DT lam, vec;          // [4, n] descending, [4, n, n] eigenvector j in column j
+    int *kept[4] = {nullptr, nullptr, nullptr, nullptr};
+    double *sg[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+void triad_isos(Step &T, const DT *grams, int d1, int d2, int rcap, DT *U, IsoKeep *ik = nullptr) {
     Ctx &c = T.c;
     const int n = d1 * d2;
     const size_t nn = (size_t)n * n;
+    if (ik) {
+        ik->truncated = n > rcap;
+        ik->n = n;
+        ik->cap = rcap;
+        ik->d1 = d1;
+        ik->d2 = d2;
+    }
     if (n <= rcap) {
         for (int i = 0; i < 4; ++i) {
             U[i] = talloc(c, {d1, d2, n});
@@ -808,6 +825,14 @@ void triad_isos(Step &T, const DT *grams, int d1, int d2, int rcap, DT *U) {
                     c.st);
         scale_cols(U[i].p, n, rcap, rcap, sg, c.st);
         U[i].d = {d1, d2, rcap};
+        if (ik) {
+            ik->kept[i] = kept;
+            ik->sg[i] = sg;
+        }
+    }
+    if (ik) {
+        ik->lam = lam;
+        ik->vec = vec;
     }
 }
 
@@ -945,9 +970,12 @@ DT coarse_half(Step &T, const DT &em, const DT &fp, const DT &t23) {
     return out;
 }
 
-// pieces of a triad step that the impurity tangents reuse (held fixed)
+// pieces of a triad step that the impurity tangents reuse (squeezers held;
+// the isometries' eigenbases for their tangents)
 struct TriadKeep {
     DT UA, UX, UY, UD, M2, N2, f, hh, em, fp, ijmm, hn, gp, klnn;
+    DT M0, M1, N0, N1, xsx, ysy;
+    IsoKeep iso;
 };
 
 void triad_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi, TriadKeep *keep = nullptr) {
@@ -976,7 +1004,8 @@ void triad_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi, Tr
     DT gd = contract(c, dy, "xijtb", Dm, "xkltb", "ijkl");
     DT grams[4] = {ga, gx, gy, gd}, Us[4];
     for (auto &gg : grams) gg.d = {d1 * d2, d1 * d2};
-    triad_isos(T, grams, d1, d2, rcap, Us);
+    IsoKeep ik;
+    triad_isos(T, grams, d1, d2, rcap, Us, keep ? &ik : nullptr);
     DT &UA = Us[0], &UX = Us[1], &UY = Us[2], &UD = Us[3];
     // triad tensors
     DT e = contract(c, A, "xijta", UA, "ijk", "xkta");
@@ -1023,7 +1052,8 @@ void triad_coarse(Step &T, const Split &sp, const Swap &sw, DT &phi, DT &psi, Tr
     DT hn = contract(c, hh, "xDsb", N[2], "tsc", "xDcbt");              // [x, kD, k3, beta, t]
     DT gp = permuted(c, g, "bYtg", "btYg");                             // [beta, t, kY, g]
     psi = coarse_half(T, hn, gp, klnn);
-    if (keep) *keep = TriadKeep{UA, UX, UY, UD, M[2], N[2], f, hh, em, fp, ijmm, hn, gp, klnn};
+    if (keep) *keep = TriadKeep{UA, UX, UY, UD, M[2], N[2], f, hh, em, fp, ijmm, hn, gp, klnn,
+                                M[0], M[1], N[0], N[1], xsx, ysy, ik};
 }
 
 // ---------------------------------------------------------------- impurity tangents
@@ -1033,11 +1063,130 @@ void axpy_scale(Ctx &c, DT &y, const DT *x, double a, const double *cdev) {
     TRG_HIP_CHECK(hipGetLastError());
 }
 
+// C[j, i] (n x cap) = P[j, i] / (lam_i - lam_j) for a kept i < *kept and a
+// discarded j >= *kept, else 0
+__global__ void iso_coef_kernel(const double *P, const double *lam, const int *kept, int n, int cap, double *C) {
+    const long tot = (long)n * cap;
+    const int k = *kept;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const int j = (int)(e / cap), i = (int)(e - (long)j * cap);
+        double v = 0.0;
+        if (i < k && j >= k) {
+            const double den = lam[i] - lam[j];
+            v = den != 0.0 ? P[(long)j * n + i] / den : 0.0;
+        }
+        C[e] = v;
+    }
+}
+
+// out[p, i] = vec[p, i] / lam[i] for the kept i < *kept, else 0 (n x cap)
+__global__ void kept_over_lam_kernel(const double *vec, const double *lam, const int *kept, int n, int cap,
+                                     double *out) {
+    const long tot = (long)n * cap;
+    const int k = *kept;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const int p = (int)(e / cap), i = (int)(e - (long)p * cap);
+        out[e] = (i < k && lam[i] != 0.0) ? vec[(long)p * n + i] / lam[i] : 0.0;
+    }
+}
+
+// g += g^T over the two halves of its labels ("ab" or "ijkl")
+void sym_add(Ctx &c, DT &g, const std::string &lab, const std::string &swp) {
+    DT t = permuted(c, g, lab, swp);
+    axpy_scale(c, g, &t, 1.0, nullptr);
+}
+
+// Tangents dU of the four triad isometries (eq. HOSVD) along the step's
+// tangents dA, d(X sigma), dY, dD (step order).  The coarse tensor depends on
+// an isometry only through its projector U U^T, so only the motion of the kept
+// subspace counts: dU = W C with W the discarded eigenvectors of the Gram and
+// C[j, i] = w_j^T dG u_i / (lam_i - lam_j) (first-order perturbation of an
+// invariant subspace), in the kept columns' sign convention.  The pivoted-
+// Cholesky eigensolver returns zero columns for a rank-deficient Gram's null
+// space, so that part of W enters as (1 - V V^T) dG u_i / lam_i (its
+// eigenvalues are 0).  The Gram tangents follow from M_k = X sigma Y^T: X sigma^2 X^T = M_k M_k^T moves by
+// d(X sigma)(X sigma)^T + transpose, Y sigma^2 Y^T = M_k^T M_k by
+// Y Wg Y^T + dY sigma^2 Y^T + transpose, Wg = (X sigma)^T d(X sigma) + transpose.
+void iso_tangents(Step &T, const TriadKeep &K, const DT &A, const Swap &sw, const DT &Dm, const DT &dA,
+                  const DT &dxs, const DT &dY, const DT &dDm, DT *dU) {
+    Ctx &c = T.c;
+    const DT &X = sw.X, &Y = sw.Y;
+    const int ng = sw.sig.d[0];
+    DT s2 = talloc(c, {ng});
+    hipLaunchKernelGGL(square_kernel, dim3(g1(ng)), dim3(256), 0, c.st, sw.sig.p, s2.p, ng);
+    DT xs = talloc(c, X.d);
+    copy(xs.p, X.p, X.n(), c.st);
+    scale_axis(xs.p, xs.d, 4, sw.sig.p, 1, c.st);
+    DT dys2 = talloc(c, dY.d);
+    copy(dys2.p, dY.p, dY.n(), c.st);
+    scale_axis(dys2.p, dys2.d, 4, s2.p, 1, c.st);
+    DT dxsx = contract(c, dxs, "aijtg", xs, "bijtg", "ab");
+    sym_add(c, dxsx, "ab", "ba");
+    DT wg = contract(c, xs, "aijtg", dxs, "aijth", "gh");
+    sym_add(c, wg, "gh", "hg");
+    DT yw = contract(c, Y, "aijtg", wg, "gh", "aijth");
+    DT dysy = contract(c, dys2, "aijtg", Y, "bijtg", "ab");
+    sym_add(c, dysy, "ab", "ba");
+    DT ywy = contract(c, yw, "aijth", Y, "bijth", "ab");
+    axpy_scale(c, dysy, &ywy, 1.0, nullptr);
+    DT dg[4];
+    {   // A: sym(dA xsx A) + A dxsx A
+        DT t = contract(c, dA, "xijta", K.xsx, "ab", "xijtb");
+        dg[0] = contract(c, t, "xijtb", A, "xkltb", "ijkl");
+        sym_add(c, dg[0], "ijkl", "klij");
+        DT t2 = contract(c, A, "xijta", dxsx, "ab", "xijtb");
+        DT g2 = contract(c, t2, "xijtb", A, "xkltb", "ijkl");
+        axpy_scale(c, dg[0], &g2, 1.0, nullptr);
+    }
+    dg[1] = contract(c, dxs, "aijtg", xs, "akltg", "ijkl");             // X: sym(d(X sigma) (X sigma))
+    sym_add(c, dg[1], "ijkl", "klij");
+    {   // Y: sym(dY s2 Y) + Y wg Y
+        dg[2] = contract(c, dys2, "aijtg", Y, "akltg", "ijkl");
+        sym_add(c, dg[2], "ijkl", "klij");
+        DT g2 = contract(c, yw, "aijth", Y, "aklth", "ijkl");
+        axpy_scale(c, dg[2], &g2, 1.0, nullptr);
+    }
+    {   // D: sym(dD ysy D) + D dysy D
+        DT t = contract(c, dDm, "xijta", K.ysy, "ab", "xijtb");
+        dg[3] = contract(c, t, "xijtb", Dm, "xkltb", "ijkl");
+        sym_add(c, dg[3], "ijkl", "klij");
+        DT t2 = contract(c, Dm, "xijta", dysy, "ab", "xijtb");
+        DT g2 = contract(c, t2, "xijtb", Dm, "xkltb", "ijkl");
+        axpy_scale(c, dg[3], &g2, 1.0, nullptr);
+    }
+    const IsoKeep &ik = K.iso;
+    const int n = ik.n, cap = ik.cap;
+    for (int i = 0; i < 4; ++i) {
+        DT V{ik.vec.p + (size_t)i * n * n, {n, n}};
+        dg[i].d = {n, n};
+        DT p1 = contract(c, V, "pj", dg[i], "pq", "jq");
+        DT pm = contract(c, p1, "jq", V, "qi", "ji");
+        DT cm = talloc(c, {n, cap});
+        hipLaunchKernelGGL(iso_coef_kernel, dim3(g1((long)n * cap)), dim3(256), 0, c.st, pm.p, ik.lam.p + (size_t)i * n,
+                           ik.kept[i], n, cap, cm.p);
+        TRG_HIP_CHECK(hipGetLastError());
+        dU[i] = contract(c, V, "pj", cm, "ji", "pi");
+        // null space of the Gram (zero eigenvector columns): (1 - V V^T) dG U / lam
+        DT ul = talloc(c, {n, cap});
+        hipLaunchKernelGGL(kept_over_lam_kernel, dim3(g1((long)n * cap)), dim3(256), 0, c.st, V.p,
+                           ik.lam.p + (size_t)i * n, ik.kept[i], n, cap, ul.p);
+        TRG_HIP_CHECK(hipGetLastError());
+        DT y1 = contract(c, dg[i], "pq", ul, "qi", "pi");
+        DT vy = contract(c, V, "qj", y1, "qi", "ji");
+        DT vvy = contract(c, V, "pj", vy, "ji", "pi");
+        axpy_scale(c, y1, &vvy, -1.0, nullptr);
+        axpy_scale(c, dU[i], &y1, 1.0, nullptr);
+        scale_cols(dU[i].p, n, cap, cap, ik.sg[i], c.st);
+        dU[i].d = {ik.d1, ik.d2, cap};
+    }
+}
+
 // One triad step of an impurity tangent (dPhi, dPsi) of the state: the pure
-// step's isometries, squeezers and norm are held; the re-split and bond-swap
-// tangents live in the tangent space of the rank-chi matrices (re-split gauge
-// A^T dA = 0, D^T dD = 0; bond swap d(X sigma) = dM Y, dY = (1 - Y Y^T) dM^T X
-// sigma^+).  Returns the new tangent in step order [x, k1, k2, k3, g].
+// step's squeezers and norm are held; the re-split and bond-swap tangents live
+// in the tangent space of the rank-chi matrices (re-split gauge A^T dA = 0,
+// D^T dD = 0; bond swap d(X sigma) = dM Y, dY = (1 - Y Y^T) dM^T X sigma^+);
+// the triad isometries move with their Grams (iso_tangents) where they
+// truncate.  Returns the new tangent in step order [x, k1, k2, k3, g].
 void triad_tangent(Step &T, const Split &sp, const Swap &sw, const TriadKeep &K, const double *dphi_p,
                    const double *dpsi_p, const std::vector<int> &order, DT &dphi_out, DT &dpsi_out) {
     trg_state *S = T.S;
@@ -1114,16 +1263,53 @@ void triad_tangent(Step &T, const Split &sp, const Swap &sw, const TriadKeep &K,
     DT df = contract(c, dxs, "aijtg", K.UX, "ijk", "aktg");
     DT dg = contract(c, dmx, "bijtg", K.UY, "ijk", "bktg");
     DT dh = contract(c, dDm, "xijtb", K.UD, "ijk", "xktb");
+    DT dijmm, dklnn;
+    if (K.iso.truncated) {
+        // the isometries' kept subspaces move with the triad Grams (see iso_tangent)
+        DT dU[4];
+        iso_tangents(T, K, sp.A, sw, sp.Dm, dA, dxs, dmx, dDm, dU);
+        DT xs = talloc(c, X.d);
+        copy(xs.p, X.p, X.n(), c.st);
+        scale_axis(xs.p, xs.d, 4, sw.sig.p, 1, c.st);
+        DT de2 = contract(c, sp.A, "xijta", dU[0], "ijk", "xkta");
+        DT df2 = contract(c, xs, "aijtg", dU[1], "ijk", "aktg");
+        DT dg2 = contract(c, Y, "bijtg", dU[2], "ijk", "bktg");
+        DT dh2 = contract(c, sp.Dm, "xijtb", dU[3], "ijk", "xktb");
+        axpy_scale(c, de, &de2, 1.0, nullptr);
+        axpy_scale(c, df, &df2, 1.0, nullptr);
+        axpy_scale(c, dg, &dg2, 1.0, nullptr);
+        axpy_scale(c, dh, &dh2, 1.0, nullptr);
+        // and so do the triad tensors I..L inside T23 (makeMG) and its makeMH counterpart
+        auto t23 = [&](const DT &u1, const DT &m0, const DT &m1, const DT &u2, const char *out) {
+            DT im = contract(c, u1, "ijA", m0, "ipk", "jApk");
+            DT imm = contract(c, im, "jApk", m1, "jql", "Apkql");
+            return contract(c, imm, "Apkql", u2, "pqX", out);
+        };
+        dijmm = t23(dU[0], K.M0, K.M1, K.UX, "AXkl");
+        DT dijmm2 = t23(K.UA, K.M0, K.M1, dU[1], "AXkl");
+        axpy_scale(c, dijmm, &dijmm2, 1.0, nullptr);
+        dklnn = t23(dU[2], K.N0, K.N1, K.UD, "XAkl");          // [kD, kY, k1, k2] as klnn
+        DT dklnn2 = t23(K.UY, K.N0, K.N1, dU[3], "XAkl");
+        axpy_scale(c, dklnn, &dklnn2, 1.0, nullptr);
+    }
     DT dem = contract(c, de, "xAta", K.M2, "tsc", "xAcas");
     DT dfp = permuted(c, df, "aXsg", "asXg");
     dphi_out = coarse_half(T, dem, K.fp, K.ijmm);
     DT t2 = coarse_half(T, K.em, dfp, K.ijmm);
     axpy_scale(c, dphi_out, &t2, 1.0, nullptr);
+    if (K.iso.truncated) {
+        DT t4 = coarse_half(T, K.em, K.fp, dijmm);
+        axpy_scale(c, dphi_out, &t4, 1.0, nullptr);
+    }
     DT dhn = contract(c, dh, "xDsb", K.N2, "tsc", "xDcbt");
     DT dgp = permuted(c, dg, "bYtg", "btYg");
     dpsi_out = coarse_half(T, dhn, K.gp, K.klnn);
     DT t3 = coarse_half(T, K.hn, dgp, K.klnn);
     axpy_scale(c, dpsi_out, &t3, 1.0, nullptr);
+    if (K.iso.truncated) {
+        DT t5 = coarse_half(T, K.hn, K.gp, dklnn);
+        axpy_scale(c, dpsi_out, &t5, 1.0, nullptr);
+    }
 }
 
 // numerical status flag (dint[0]) -> error
