@@ -46,7 +46,7 @@ extern "C" {
 #define TRG_E_NUMERICAL -4   /* NaN/Inf, non-positive norm, Jacobi not converged in max_sweeps       */
 #define TRG_E_HIP       -5   /* HIP runtime error (message kept in trg_last_error)                    */
 #define TRG_E_UNSUPPORTED -6 /* a shape outside the kernels' documented limits                       */
-#define TRG_E_MULTIPLET -7   /* a truncation cut falls inside a multiplet of more than 16 values      */
+#define TRG_E_MULTIPLET -7   /* a truncation cut falls inside a multiplet of more than 32 values      */
 
 /* ---- options ---------------------------------------------------------- */
 #define TRG_MODEL_ISING 0

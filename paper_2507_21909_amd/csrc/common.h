@@ -94,10 +94,12 @@ void sign_vector(const double *q, long rows, int cols, long ld, const std::vecto
                  const std::vector<double> &pw, double *sg, double *ws, hipStream_t st);
 // scratch for the weight sums of `cols` columns of `rows` rows with L weights
 size_t weight_ws_doubles(long rows, int cols, int L);
+// largest multiplet the canonical basis forms (a cut inside a larger one sets status 2)
+constexpr int CANON_L = 32;
 // Canonical basis within multiplets: rot (cols x cols, block diagonal) such that
 // q rot has, in every group of the first *k_dev values closer than tau * vals[0],
 // the columns Q_m Q_z with Q_z the Q factor of Q_m^T W (fixed weights w_l of the
-// row multi-index).  z_work holds weight_ws_doubles(rows, cols, 16) doubles;
+// row multi-index).  z_work holds weight_ws_doubles(rows, cols, CANON_L) doubles;
 // status gets 2 if a group is larger than 16.
 void canonical_rotation(const double *q, long rows, int cols, long ld, const std::vector<int> &dims,
                         const std::vector<double> &pw, const double *vals, const int *k_dev, double tau,

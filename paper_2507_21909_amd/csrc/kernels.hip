@@ -195,22 +195,24 @@ __global__ void sketch_kernel(double *out, SketchArgs a) {
 }
 
 // Z[j][l] = sum_i Q[i, j] w_l(i), w_l(i) = 0.5 + frac(g (1 + code(i)) + l (sqrt 2 - 1)),
-// l < L <= 16, with code(i) = sum_d idx_d(i) pw_d over the row multi-index.
+// l < L <= LM (1 for the sign vectors, CANON_L for the canonical bases), with
+// code(i) = sum_d idx_d(i) pw_d over the row multi-index.
 // First pass: workgroup (x, y) takes 64 columns and the y-th chunk of rpb rows;
 // each wavefront reads whole 64-column row segments (coalesced), every 4th row
 // of the chunk, and the 4 wavefronts' sums are added in a fixed order into
 // part[(y * cols + j) * L + l].  Second pass: Z = the chunk partials added in
 // chunk order (and, with sg, the sign of Z[j][0]).  Both orders are fixed, so
 // the sums are the same bits on every run.
+template <int LM>
 __global__ __launch_bounds__(256) void weights_partial_kernel(const double *q, long rows, int cols, long ld,
                                                               SignArgs a, int L, long rpb, double *part) {
     const double golden = 0.6180339887498949, c2 = 0.41421356237309515;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int j = blockIdx.x * 64 + lane;
     const long r0 = (long)blockIdx.y * rpb, r1 = r0 + rpb < rows ? r0 + rpb : rows;
-    double acc[16];
+    double acc[LM];
 #pragma unroll
-    for (int l = 0; l < 16; ++l) acc[l] = 0.0;
+    for (int l = 0; l < LM; ++l) acc[l] = 0.0;
     for (long r = r0 + w; r < r1; r += 4) {
         long rem = r;
         double code = 0.0;
@@ -222,15 +224,15 @@ __global__ __launch_bounds__(256) void weights_partial_kernel(const double *q, l
         const double x = golden * (1.0 + code);
         const double v = j < cols ? q[r * ld + j] : 0.0;
 #pragma unroll
-        for (int l = 0; l < 16; ++l)
+        for (int l = 0; l < LM; ++l)
             if (l < L) {
                 const double y = x + l * c2;
                 acc[l] += (0.5 + (y - floor(y))) * v;
             }
     }
-    __shared__ double red[4][64][17];
+    __shared__ double red[4][64][LM + 1];
 #pragma unroll
-    for (int l = 0; l < 16; ++l)
+    for (int l = 0; l < LM; ++l)
         if (l < L) red[w][lane][l] = acc[l];
     __syncthreads();
     if (w == 0 && j < cols)
@@ -264,9 +266,9 @@ __global__ void canon_rot_kernel(const double *v, int n, const int *kdev, double
         if (d > L) {
             *status = 2;
         } else {
-            double qm[16][16];
+            double qm[CANON_L][CANON_L];
             for (int c = 0; c < d; ++c) {
-                double col[16];
+                double col[CANON_L];
                 for (int r = 0; r < d; ++r) col[r] = z[(long)(a + r) * L + c];
                 for (int pass = 0; pass < 2; ++pass)
                     for (int p = 0; p < c; ++p) {
@@ -442,9 +444,10 @@ void weight_sums(const double *q, long rows, int cols, long ld, const SignArgs &
                  double *sg, hipStream_t st) {
     const long rpb = weight_rpb(rows);
     const int nchunk = (int)((rows + rpb - 1) / rpb);
-    TRG_REQUIRE(L >= 1 && L <= 16, -1, "weight sums: L out of range");
+    TRG_REQUIRE(L == 1 || L == CANON_L, -1, "weight sums: L must be 1 or CANON_L");
     dim3 grid((cols + 63) / 64, nchunk);
-    hipLaunchKernelGGL(weights_partial_kernel, grid, dim3(256), 0, st, q, rows, cols, ld, a, L, rpb, ws);
+    if (L == 1) hipLaunchKernelGGL(weights_partial_kernel<1>, grid, dim3(256), 0, st, q, rows, cols, ld, a, L, rpb, ws);
+    else hipLaunchKernelGGL(weights_partial_kernel<CANON_L>, grid, dim3(256), 0, st, q, rows, cols, ld, a, L, rpb, ws);
     hipLaunchKernelGGL(weights_final_kernel, dim3((cols * L + 255) / 256), dim3(256), 0, st, ws, nchunk, cols, L,
                        z, sg);
     TRG_HIP_CHECK(hipGetLastError());
@@ -506,7 +509,7 @@ void canonical_rotation(const double *q, long rows, int cols, long ld, const std
     for (int i = 0; i < a.nd; ++i) { a.dd[i] = dims[i]; a.pw[i] = pw[i]; prod *= dims[i]; }
     TRG_REQUIRE(prod == rows, -1, "canonical_rotation: dims do not match rows");
     if (cols == 0) return;
-    const int L = 16;
+    const int L = CANON_L;
     double *z = z_work, *part = z_work + (size_t)cols * L;
     weight_sums(q, rows, cols, ld, a, L, part, z, nullptr, st);
     hipLaunchKernelGGL(canon_rot_kernel, dim3(1), dim3(64), 0, st, vals, cols, k_dev, tau, z, L, rot, status);

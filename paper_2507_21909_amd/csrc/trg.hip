@@ -381,7 +381,7 @@ Split resplit(Step &T, const std::vector<int> &order) {
     kept_count(s.p, chi, chi, 0.0, -1.0, kpos, c.st);           // number of s > 0
     std::vector<int> nd(S->dims.begin(), S->dims.end());
     DT rot = talloc(c, {chi, chi});
-    double *zw = c.ar->dalloc(weight_ws_doubles(F, chi, 16));
+    double *zw = c.ar->dalloc(weight_ws_doubles(F, chi, CANON_L));
     canonical_rotation(A.p, F, chi, chi, nd, pow131(d), s.p, kpos, T.S->opt.tau_deg, zw, rot.p, S->dint, c.st);
     DT A2 = contract(c, A, "Fa", rot, "ab", "Fb");
     DT D2 = contract(c, Dm, "Fa", rot, "ab", "Fb");
@@ -696,7 +696,7 @@ void squeezers(Step &T, const double *kf, const double *kb, int cnt, int dt, int
         scale_axis(ud.p, ud.d, 1, is.p, 1, c.st);
         // canonical basis of the new leg within multiplets of S
         DT rot = talloc(c, {D, D});
-        double *zw = c.ar->dalloc(weight_ws_doubles(n, D, 16));
+        double *zw = c.ar->dalloc(weight_ws_doubles(n, D, CANON_L));
         canonical_rotation(vd.p, n, D, D, {dt, db}, {1.0, 131.0}, si, kept, T.S->opt.tau_deg, zw, rot.p, S->dint, c.st);
         E[i] = contract(c, vd, "pk", rot, "kl", "pl");
         E[i].d = {dt, db, D};
@@ -1316,7 +1316,7 @@ void triad_tangent(Step &T, const Split &sp, const Swap &sw, const TriadKeep &K,
 void check_status(int status) {
     TRG_REQUIRE(status != 1, TRG_E_NUMERICAL, "non-positive or non-finite norm at a re-split");
     TRG_REQUIRE(status != 2, TRG_E_MULTIPLET,
-                "a truncation cut falls in a multiplet of more than 16 values (canonical basis not formed); "
+                "a truncation cut falls in a multiplet of more than 32 values (canonical basis not formed); "
                 "change tau_deg or D");
     TRG_REQUIRE(status != 3, TRG_E_NUMERICAL,
                 "Jacobi SVD of a replayed step not converged within the sweeps allowed at capture");
