@@ -916,9 +916,20 @@ DT coarse_half_planes(Step &T, const DT &em, const DT &fp, const DT &t23) {
     return out;
 }
 
-DT coarse_half(Step &T, const DT &em, const DT &fp, const DT &t23) {
+// em2 / fp2 (optional, same shapes): out = (EM F + EM2 F2) T23, the second K1
+// added into the same Z before K2 (one K2 for both products)
+DT coarse_half(Step &T, const DT &em, const DT &fp, const DT &t23, const DT *em2 = nullptr, const DT *fp2 = nullptr) {
     Ctx &c = T.c;
-    if (c.prec == P_BF16X6) return coarse_half_planes(T, em, fp, t23);
+    if (c.prec == P_BF16X6) {
+        DT out = coarse_half_planes(T, em, fp, t23);
+        if (em2) {
+            DT o2 = coarse_half_planes(T, *em2, *fp2, t23);
+            hipLaunchKernelGGL(axpy_scale_kernel, dim3(g1(out.n())), dim3(256), 0, c.st, out.p, o2.p, out.n(), 1.0,
+                               nullptr);
+            TRG_HIP_CHECK(hipGetLastError());
+        }
+        return out;
+    }
     const int X = em.d[0], U = em.d[1], C = em.d[2], Aa = em.d[3], Ss = em.d[4];
     const int V = fp.d[2], G = fp.d[3];
     const int Kk = t23.d[2], Ll = t23.d[3];
@@ -945,6 +956,14 @@ DT coarse_half(Step &T, const DT &em, const DT &fp, const DT &t23) {
         g.cN2 = G; g.sCn = (long)C * G; g.sCn2 = 1;
         g.alpha = 1.0; g.beta = 0.0;
         timed_gemm(c, g, c.prec);
+        if (em2) {
+            TRG_REQUIRE(em2->d == em.d && fp2->d == fp.d, -1, "coarse_half: second product's shapes");
+            GemmArgs g2 = g;
+            g2.A = em2->p + (long)x0 * U * C * Aa * Ss;
+            g2.B = fp2->p;
+            g2.beta = 1.0;
+            timed_gemm(c, g2, c.prec);
+        }
         // K2 has few output tiles (D^2 x D^2 per slab) over a long K = R^2: split K
         // so the launch fills the CUs, then add the slices in a fixed order
         const long mn = (long)Kk * Ll * C * G;
@@ -1294,18 +1313,14 @@ void triad_tangent(Step &T, const Split &sp, const Swap &sw, const TriadKeep &K,
     }
     DT dem = contract(c, de, "xAta", K.M2, "tsc", "xAcas");
     DT dfp = permuted(c, df, "aXsg", "asXg");
-    dphi_out = coarse_half(T, dem, K.fp, K.ijmm);
-    DT t2 = coarse_half(T, K.em, dfp, K.ijmm);
-    axpy_scale(c, dphi_out, &t2, 1.0, nullptr);
+    dphi_out = coarse_half(T, dem, K.fp, K.ijmm, &K.em, &dfp);
     if (K.iso.truncated) {
         DT t4 = coarse_half(T, K.em, K.fp, dijmm);
         axpy_scale(c, dphi_out, &t4, 1.0, nullptr);
     }
     DT dhn = contract(c, dh, "xDsb", K.N2, "tsc", "xDcbt");
     DT dgp = permuted(c, dg, "bYtg", "btYg");
-    dpsi_out = coarse_half(T, dhn, K.gp, K.klnn);
-    DT t3 = coarse_half(T, K.hn, dgp, K.klnn);
-    axpy_scale(c, dpsi_out, &t3, 1.0, nullptr);
+    dpsi_out = coarse_half(T, dhn, K.gp, K.klnn, &K.hn, &dgp);
     if (K.iso.truncated) {
         DT t5 = coarse_half(T, K.hn, K.gp, dklnn);
         axpy_scale(c, dpsi_out, &t5, 1.0, nullptr);
