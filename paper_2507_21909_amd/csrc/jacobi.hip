@@ -407,13 +407,16 @@ __global__ void init_v_kernel(JacobiBatch jb) {
     }
 }
 
-// per-matrix max |u| -> scale[mat]; u /= scale
-__global__ void scale_kernel(JacobiBatch jb, double *scale) {
-    const int mat = blockIdx.x;
-    double *u = jb.ut + (long)mat * jb.strideU;
-    long tot = (long)jb.m * jb.n;
+// per-matrix max |u| -> scale[mat]; u /= scale.  Three passes so that the
+// whole GPU takes part (a batch holds only a few matrices): partial maxima of
+// P slices per matrix, their maximum, then the division (max is exact in any
+// order, so the result does not depend on P).
+__global__ void absmax_partial_kernel(JacobiBatch jb, int P, double *part) {
+    const int mat = blockIdx.y, b = blockIdx.x;
+    const double *u = jb.ut + (long)mat * jb.strideU;
+    const long tot = (long)jb.m * jb.n;
     double mx = 0.0;
-    for (long i = threadIdx.x; i < tot; i += blockDim.x) mx = fmax(mx, fabs(u[i]));
+    for (long i = (long)b * NT + threadIdx.x; i < tot; i += (long)P * NT) mx = fmax(mx, fabs(u[i]));
     __shared__ double red[NT];
     red[threadIdx.x] = mx;
     __syncthreads();
@@ -421,9 +424,23 @@ __global__ void scale_kernel(JacobiBatch jb, double *scale) {
         if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
-    double f = red[0] > 0.0 ? red[0] : 1.0;
-    if (threadIdx.x == 0) scale[mat] = f;
-    for (long i = threadIdx.x; i < tot; i += blockDim.x) u[i] /= f;
+    if (threadIdx.x == 0) part[(long)mat * P + b] = red[0];
+}
+
+__global__ void absmax_final_kernel(const double *part, int P, double *scale) {
+    const int mat = blockIdx.x;
+    if (threadIdx.x) return;
+    double mx = 0.0;
+    for (int b = 0; b < P; ++b) mx = fmax(mx, part[(long)mat * P + b]);
+    scale[mat] = mx > 0.0 ? mx : 1.0;
+}
+
+__global__ void divide_kernel(JacobiBatch jb, const double *scale) {
+    const long per = (long)jb.m * jb.n, tot = per * jb.count;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const long mat = e / per;
+        jb.ut[mat * jb.strideU + (e - mat * per)] /= scale[mat];
+    }
 }
 
 // norms of the columns (one wave per column)
@@ -538,7 +555,14 @@ int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *wo
                const DevLoop *dl) {
     if (jb.count == 0 || jb.n == 0) return 0;
     const double tol = sqrt((double)jb.m) * 2.220446049250313e-16;
-    hipLaunchKernelGGL(scale_kernel, dim3(jb.count), dim3(NT), 0, st, jb, work);
+    {   // the column-norm area of work (count * n doubles) holds the partial maxima
+        const int P = std::min(jb.n, 64);
+        hipLaunchKernelGGL(absmax_partial_kernel, dim3(P, jb.count), dim3(NT), 0, st, jb, P, work + jb.count);
+        hipLaunchKernelGGL(absmax_final_kernel, dim3(jb.count), dim3(64), 0, st, work + jb.count, P, work);
+        const size_t tot = (size_t)jb.count * jb.m * jb.n;
+        hipLaunchKernelGGL(divide_kernel, dim3((unsigned)std::min<size_t>(cdiv(tot, 256), 65536)), dim3(256), 0, st,
+                           jb, work);
+    }
     if (jb.vt)
         hipLaunchKernelGGL(init_v_kernel, dim3(cdiv((size_t)jb.count * jb.n * jb.n, 256)), dim3(256), 0, st, jb);
     TRG_HIP_CHECK(hipGetLastError());
