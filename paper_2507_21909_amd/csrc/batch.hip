@@ -15,6 +15,8 @@
 // steps bit for bit.
 #include <algorithm>
 #include <atomic>
+#include <cstdio>
+#include <cstdlib>
 #include <string>
 #include <thread>
 #include <vector>
@@ -54,12 +56,20 @@ int run_instance(trg_state *s, int nsteps, const int *axes, bool graphs) {
         if (rc != TRG_OK) drop();
         return rc;
     };
+    static const bool trace = [] {
+        const char *e = getenv("TRG_BATCH_TRACE");
+        return e && *e && *e != '0';
+    }();
     bool steady = false;
-    int rc = TRG_OK;
+    int rc = TRG_OK, replays = 0, fallbacks = 0;
     for (int k = 0; k < nsteps && rc == TRG_OK; ++k) {
         const int ax = axes ? axes[k] : k % 4;
         if (steady) {
-            if (trg_graph_launch(g[ax], 1) == TRG_OK) continue;
+            if (trg_graph_launch(g[ax], 1) == TRG_OK) {
+                ++replays;
+                continue;
+            }
+            ++fallbacks;
             drop();
             rc = triad_atrg_step(s, ax);
             if (rc == TRG_OK && k + 1 < nsteps) rc = record();
@@ -77,6 +87,8 @@ int run_instance(trg_state *s, int nsteps, const int *axes, bool graphs) {
         }
     }
     drop();
+    if (trace && graphs)
+        fprintf(stderr, "[batch] %d replays, %d taken eagerly after a failed replay\n", replays, fallbacks);
     return rc;
 }
 

@@ -118,12 +118,20 @@ __global__ __launch_bounds__(NT) void round_kernel(JacobiBatch jb, int r, double
     }
 }
 
+// One workgroup per matrix loops over every round and sweep.  All column
+// pairs of a round are rotated at once: pair k takes a group of tp lanes (a
+// power of two, np tp <= NT, inside one wavefront), each lane summing every
+// tp-th row, the group reducing its three dot products by an xor butterfly
+// (fixed order, so the bits do not depend on the schedule) and rotating its
+// rows of U and V; one barrier per round.
 __global__ __launch_bounds__(NT) void full_kernel(JacobiBatch jb, int max_sweeps, double tol, int *flags) {
     const int mat = blockIdx.x;
     double *u = jb.ut + (long)mat * jb.strideU;
     double *v = jb.vt ? jb.vt + (long)mat * jb.strideV : nullptr;
-    const int mm = jb.n + (jb.n & 1);
-    const int w = threadIdx.x >> 6;
+    const int n = jb.n, m = jb.m, mm = n + (n & 1), np = mm / 2;
+    int tp = 64;
+    while (tp > 1 && np * tp > NT) tp >>= 1;
+    const int k = threadIdx.x / tp, l = threadIdx.x % tp;
     __shared__ int rot, bad;
     if (threadIdx.x == 0) bad = 0;
     int sweep = 0;
@@ -131,11 +139,42 @@ __global__ __launch_bounds__(NT) void full_kernel(JacobiBatch jb, int max_sweeps
         if (threadIdx.x == 0) rot = 0;
         __syncthreads();
         for (int r = 0; r < mm - 1; ++r) {
-            for (int k = w; k < mm / 2; k += NT / 64) {
-                const int rc = rotate_pair(u, v, jb.m, jb.n, mm, r, k, tol);
-                if ((threadIdx.x & 63) == 0) {
-                    if (rc == 1) atomicAdd(&rot, 1);
-                    if (rc == 2) bad = 1;
+            const int a = k < np ? player_at(mm, k, r) : n, b = k < np ? player_at(mm, mm - 1 - k, r) : n;
+            if (a < n && b < n) {   // uniform within the lane group
+                const int p = a < b ? a : b, q = a < b ? b : a;
+                double *up = u + (long)p * m, *uq = u + (long)q * m;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = l; i < m; i += tp) {
+                    const double x = up[i], y = uq[i];
+                    al += x * x;
+                    be += y * y;
+                    ga += x * y;
+                }
+                for (int off = tp / 2; off > 0; off >>= 1) {
+                    al += __shfl_xor(al, off, 64);
+                    be += __shfl_xor(be, off, 64);
+                    ga += __shfl_xor(ga, off, 64);
+                }
+                if (!isfinite(al + be + ga)) {
+                    if (l == 0) bad = 1;
+                } else {
+                    double c, s;
+                    if (jacobi_rotation(al, be, ga, tol, c, s)) {
+                        for (int i = l; i < m; i += tp) {
+                            const double x = up[i], y = uq[i];
+                            up[i] = c * x - s * y;
+                            uq[i] = s * x + c * y;
+                        }
+                        if (v) {
+                            double *vp = v + (long)p * n, *vq = v + (long)q * n;
+                            for (int i = l; i < n; i += tp) {
+                                const double x = vp[i], y = vq[i];
+                                vp[i] = c * x - s * y;
+                                vq[i] = s * x + c * y;
+                            }
+                        }
+                        if (l == 0) atomicAdd(&rot, 1);
+                    }
                 }
             }
             __syncthreads();
