@@ -69,9 +69,8 @@ def batch_main(args):
     (j = 0..31) x h_l in {0, 1e-4, 1e-3, 1e-2}, instance i = j + 32 l, D = (8, 12, 16, 24)[i mod 4],
     r = 7, L = 2^10 per axis (40 steps).  The 128 instances run as eight trg_batch objects of 16
     (instance words 0, 16, .., 112, so every instance draws the sketches it would in one batch of
-    128), first eagerly (trg_batch_run, the reported value), then with the steady steps replayed
-    from HIP graphs (trg_batch_run_graphs); the two must agree bit for bit, and a sample of instances must equal
-    lone solves bit for bit.  The sequential time of all 128 is estimated from the sample's per-D
+    128), with trg_batch_run; a sample of instances must equal lone solves bit for bit, eagerly and
+    with their steady steps replayed from HIP graphs.  The sequential time of all 128 is estimated from the sample's per-D
     times."""
     import numpy as np
     import paper_2507_21909_amd as trg
@@ -99,12 +98,7 @@ def batch_main(args):
                                                                  16 * g + 15, wall), file=sys.stderr, flush=True)
         return out, wall
 
-    got_e, t_eager = run(False)
-    got, t_graph = run(True)
-    if not np.array_equal(got, got_e):
-        bad = int(np.flatnonzero(got != got_e)[0])
-        print("graph batch differs from the eager batch at instance %d" % bad, file=sys.stderr)
-        sys.exit(1)
+    got, t_eager = run(False)
     sample = [0, 1, 2, 3, 45, 46, 47, 60, 66, 79, 93, 98, 103, 113, 126, 127]
     t_by_d, tg_by_d = {}, {}
 
@@ -151,13 +145,12 @@ def batch_main(args):
            "value": 128 * nsteps / t_eager, "unit": "instance-steps/s", "n_gpus": 1, "steps": nsteps,
            "higher_is_better": True, "dtype": "f64", "data": "synthetic (4D Ising tensors from beta, h)",
            "config": {"workload": "128-instance beta x h scan, r=7, %d steps" % nsteps},
-           "batch_wall_s": t_eager, "graph_batch_wall_s": t_graph,
-           "graph_instance_steps_per_s": 128 * nsteps / t_graph,
+           "batch_wall_s": t_eager,
            "sequential_wall_s_estimated": t_seq,
            "sequential_instance_steps_per_s": 128 * nsteps / t_seq,
            "sequential_s_per_solve_by_D": {str(k): float(np.mean(v)) for k, v in sorted(t_by_d.items())},
            "lone_graph_s_per_solve_by_D": {str(k): float(np.mean(v)) for k, v in sorted(tg_by_d.items())},
-           "graphs_equal_eager_bitwise": 128, "bitwise_equal_sample": len(sample)}
+           "bitwise_equal_sample": len(sample)}
     print(json.dumps(out), flush=True)
 
 

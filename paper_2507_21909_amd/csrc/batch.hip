@@ -17,6 +17,7 @@
 #include <atomic>
 #include <cstdio>
 #include <cstdlib>
+#include <shared_mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -38,6 +39,12 @@ struct trg_batch {
 namespace {
 constexpr int MAX_WORKERS = 8;
 
+// Recording a step (trg_graph_capture) takes this lock exclusively and every
+// other HIP-calling part of a worker's instance shares it, so no worker calls
+// the runtime while another records (a precaution: a 128-instance run with
+// graphs once stopped making progress, cause not identified).
+std::shared_mutex hip_lock;
+
 // all nsteps of one instance: eager steps, and with graphs, checked replays of
 // recorded steps from the first step that leaves the shapes unchanged; a
 // replay that fails is rolled back by the library and the step taken eagerly
@@ -51,11 +58,13 @@ int run_instance(trg_state *s, int nsteps, const int *axes, bool graphs) {
         }
     };
     auto record = [&]() {
+        std::unique_lock<std::shared_mutex> lk(hip_lock);
         int rc = TRG_OK;
         for (int a = 0; a < 4 && rc == TRG_OK; ++a) rc = trg_graph_capture(s, TRG_METHOD_TRIAD, a, &g[a]);
         if (rc != TRG_OK) drop();
         return rc;
     };
+    auto shared = [&]() { return std::shared_lock<std::shared_mutex>(hip_lock); };
     static const bool trace = [] {
         const char *e = getenv("TRG_BATCH_TRACE");
         return e && *e && *e != '0';
@@ -65,19 +74,25 @@ int run_instance(trg_state *s, int nsteps, const int *axes, bool graphs) {
     for (int k = 0; k < nsteps && rc == TRG_OK; ++k) {
         const int ax = axes ? axes[k] : k % 4;
         if (steady) {
-            if (trg_graph_launch(g[ax], 1) == TRG_OK) {
-                ++replays;
-                continue;
+            {
+                auto lk = shared();
+                if (trg_graph_launch(g[ax], 1) == TRG_OK) {
+                    ++replays;
+                    continue;
+                }
+                ++fallbacks;
+                drop();
+                rc = triad_atrg_step(s, ax);
             }
-            ++fallbacks;
-            drop();
-            rc = triad_atrg_step(s, ax);
             if (rc == TRG_OK && k + 1 < nsteps) rc = record();
             continue;
         }
         int d0[4], c0 = 0, d1[4], c1 = 0;
         if (graphs) rc = trg_shape(s, d0, &c0, nullptr);
-        if (rc == TRG_OK) rc = triad_atrg_step(s, ax);
+        if (rc == TRG_OK) {
+            auto lk = shared();
+            rc = triad_atrg_step(s, ax);
+        }
         if (rc == TRG_OK && graphs) {
             rc = trg_shape(s, d1, &c1, nullptr);
             if (rc == TRG_OK && c0 == c1 && std::equal(d0, d0 + 4, d1) && k + 1 < nsteps) {
@@ -86,7 +101,10 @@ int run_instance(trg_state *s, int nsteps, const int *axes, bool graphs) {
             }
         }
     }
-    drop();
+    {
+        auto lk = shared();
+        drop();
+    }
     if (trace && graphs)
         fprintf(stderr, "[batch] %d replays, %d taken eagerly after a failed replay\n", replays, fallbacks);
     return rc;
@@ -110,7 +128,10 @@ int run_all(trg_batch *b, int nsteps, const int *axes, bool graphs) {
                 int expect = TRG_OK;
                 first_rc.compare_exchange_strong(expect, rc);
             }
-            (void)trg_release_workspace(b->s[i]);   // bounded memory: one workspace per worker
+            {   // bounded memory: one workspace per worker
+                std::shared_lock<std::shared_mutex> lk(hip_lock);
+                (void)trg_release_workspace(b->s[i]);
+            }
         }
     };
     std::vector<std::thread> pool;
