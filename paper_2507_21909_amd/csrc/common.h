@@ -162,6 +162,9 @@ struct DevLoop {
 // 2 * count + 1 ints.  With dl the return value is -1 (sweeps not known on the host).
 int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *work, hipStream_t st,
                const DevLoop *dl = nullptr);
+// true when jacobi_svd solves the batch in a single launch (its sweeps loop on
+// the device; no sweep cap is needed when it is recorded)
+bool jacobi_one_launch(const JacobiBatch &jb);
 // After jacobi_svd: s (count x n) descending singular values, U columns normalized
 // and sorted into u_sorted (row-major m x n, may be null), V sorted into v_sorted
 // (row-major n x n).

@@ -589,6 +589,8 @@ bool trace_on() {
 }
 }  // namespace
 
+bool jacobi_one_launch(const JacobiBatch &jb) { return jb.n <= 96; }
+
 // flags_dev: 2 * count + 1 ints of device scratch
 int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *work, hipStream_t st,
                const DevLoop *dl) {
@@ -607,7 +609,7 @@ int jacobi_svd(const JacobiBatch &jb, int max_sweeps, int *flags_dev, double *wo
     TRG_HIP_CHECK(hipGetLastError());
     const int mm = jb.n + (jb.n & 1);
     std::vector<int> fl(2 * jb.count);
-    if (jb.n <= 96) {
+    if (jacobi_one_launch(jb)) {
         hipLaunchKernelGGL(full_kernel, dim3(jb.count), dim3(NT), 0, st, jb, max_sweeps, tol, flags_dev);
         TRG_HIP_CHECK(hipGetLastError());
         if (dl) {

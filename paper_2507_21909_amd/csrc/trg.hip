@@ -254,10 +254,11 @@ void col_slice(Ctx &c, const double *src, long rows, long cols, int k, double *d
 // One-sided Jacobi under the step's convergence policy.  Eager: the host reads
 // every sweep's rotation count and the sweeps used are logged for the solve
 // (its call order in the step and its shape).  Captured: nothing is read back;
-// the panel solver runs device-driven up to twice the most sweeps logged for
-// the same solve, plus 8 (status 3 if that is not enough: a squeezer solve can
-// take 10 sweeps in one step and 40 a few steps later), the one-launch solver
-// up to max_sweeps as eagerly.
+// the panel solver (more than 96 columns) runs
+// device-driven up to twice the most sweeps logged for the same solve, plus 8
+// (status 3 if that is not enough: a squeezer solve can take 10 sweeps in one
+// step and 40 a few steps later), the one-launch solver up to max_sweeps as
+// eagerly.
 int run_jacobi(Ctx &c, const JacobiBatch &jb, int ms, int *flags, double *work) {
     const std::array<int, 4> key{c.solve_idx++, jb.count, jb.m, jb.n};
     if (!c.capture) {
@@ -269,7 +270,7 @@ int run_jacobi(Ctx &c, const JacobiBatch &jb, int ms, int *flags, double *work) 
         return sw;
     }
     int cap = ms;
-    if (jb.n > 96) {
+    if (!jacobi_one_launch(jb)) {
         auto it = c.sweep_log ? c.sweep_log->find(key) : std::map<std::array<int, 4>, int>::iterator();
         TRG_REQUIRE(c.sweep_log && it != c.sweep_log->end(), TRG_E_STATE,
                     "graph capture: no eager step of this method at these shapes has run on the state");
@@ -277,7 +278,7 @@ int run_jacobi(Ctx &c, const JacobiBatch &jb, int ms, int *flags, double *work) 
     }
     const char *env = getenv("TRG_GRAPH_SWEEP_CAP");   // test hook: a smaller cap for recorded solves
     const int forced = env && *env ? atoi(env) : 0;
-    if (forced > 0 && jb.n > 96) cap = std::min(cap, forced);
+    if (forced > 0 && !jacobi_one_launch(jb)) cap = std::min(cap, forced);
     DevLoop dl{cap, c.dstatus, 3};
     return jacobi_svd(jb, ms, flags, work, c.st, &dl);
 }
