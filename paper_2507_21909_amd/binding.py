@@ -57,6 +57,14 @@ def load_library(path=None):
     path = path or LIB_PATH
     if not os.path.exists(path):
         raise FileNotFoundError("libtrg.so not built: run paper_2507_21909_amd/build.py (%s)" % path)
+    # torch ships its own HIP runtime under the same soname: loaded first, it
+    # is the one libtrg.so binds to, so the process holds a single runtime and
+    # torch's device pointers are valid in the library (loaded the other way
+    # round, two runtimes would each claim the GPU and torch's fails to start)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     st = ctypes.c_void_p
     lib.trg_default_options.argtypes = [ctypes.POINTER(Options)]

@@ -3,19 +3,16 @@
 // (App. A, eq. bond1 / bond2) and, in exact mode, the QR of B and C (App. A).
 //
 // Level l splits its rows into blocks of 256 rows; one workgroup factors a
-// block with Householder reflections (LAPACK dlarfg / dlarf order), one row of
-// the block per thread held in registers, and writes the n x n R factor and
-// the explicit 256 x n thin Q (dorg2r order).  The reflectors wait in the
-// block's own rows of the Q output (each thread reads back only its row), so
-// the kernel needs no large LDS buffer and, at up to 256 registers per lane,
-// two blocks share a CU and hide each other's reduction latency.  The stacked R factors are the
-// next level's input; the last level (one block) fixes diag(R) >= 0.  Q is
-// then rebuilt top-down: Q_l[block b] = Q_l,b * Q_{l+1}[b*n:(b+1)*n, :], a
-// batched GEMM per level.
+// block with Householder reflections (LAPACK dlarfg / dlarf order) and writes
+// the n x n R factor and the explicit 256 x n thin Q (dorg2r order).  The
+// stacked R factors are the next level's input; the last level (one block)
+// fixes diag(R) >= 0.  Q is then rebuilt top-down: Q_l[block b] = Q_l,b *
+// Q_{l+1}[b*n:(b+1)*n, :], a batched GEMM per level.
 #include <cmath>
 
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 #include "common.h"
 
@@ -23,153 +20,186 @@ namespace trg {
 
 namespace {
 constexpr int NT = 256;
-
-// Block factorisation: one row of the 256-row block per thread (NC >= n
-// columns in registers), Householder column by column with the dot products of
-// the reflector with every column (v^T A) reduced at once: a reduce-scatter
-// butterfly across the wavefront, then the 4 wavefronts in LDS.
 constexpr int RB = 256;   // rows per block
 
-// reduce-scatter halving steps: CNT live values in v[0..CNT); the partner
-// (lane ^ off) keeps the other half; all indices compile-time.  The first step
-// (off 32) is wg_sum's own, so v holds NC / 2 values
-template <int NC, int CNT>
-__device__ inline void halve_rest(double (&v)[NC / 2], int lane, int &idx) {
-    if constexpr (CNT > 1) {
-        constexpr int half = CNT / 2, off = 32 * CNT / NC;
-        const bool hi = lane & off;
-#pragma unroll
-        for (int i = 0; i < half; ++i) {
-            const double send = hi ? v[i] : v[half + i], keep = hi ? v[half + i] : v[i];
-            v[i] = keep + __shfl_xor(send, off, 64);
-        }
-        idx += hi ? half : 0;
-        halve_rest<NC, half>(v, lane, idx);
+// Block factorisation with the block's columns spread over the workgroup: a
+// group of TPC = NTH / NC adjacent lanes owns column c, lane q of the group
+// holding rows TPC i + q (i < RPT = 256 / TPC) in registers, so every dot
+// product of a column with the reflector is RPT fused multiply-adds in a lane
+// and a log2(TPC)-step butterfly inside the group.  Step j: the lanes of
+// column j form the reflector (norm by the same butterfly) and write it, zero
+// above row j, to LDS; after one barrier every column right of j reads it
+// there and updates itself, and the workgroup copies it, one row a thread,
+// to the block's Q output.  Runs of SK registers whose rows all lie above j
+// are skipped (a workgroup-uniform test).  The reflector buffer alternates
+// between two slots, so a step needs no second barrier.  Q = H_0 ... H_{n-1}
+// [I; 0] is then built the same way, column c of Q in the registers of column
+// c's lanes.  1024 threads keep the per-step chain at 16 rows a lane.
+// Row tests are written as TPC i against a per-lane offset (j - q, n - q, ...)
+// so that no per-register row index is held in registers.
+constexpr int NTH = 1024;
+
+// pairwise (tree) sum of f(L) .. f(L + N - 1), N a power of two, with every
+// index a compile-time constant so that f can pick registers.  The left half
+// is finished before the right half's loads start (an empty asm with a memory
+// clobber), which keeps the register count of a sequential sum
+template <int L, int N, class F>
+__device__ __forceinline__ double tree_sum(const F &f) {
+    if constexpr (N == 1) {
+        return f(std::integral_constant<int, L>{});
+    } else {
+        double lo = tree_sum<L, N / 2>(f);
+        asm volatile("" : "+v"(lo) : : "memory");
+        return lo + tree_sum<L + N / 2, N / 2>(f);
     }
 }
 
-// sum over the workgroup of s * x[0..NC) (per thread); result in out[0..NC)
-// (LDS).  The first halving step reads s * x directly, so the products never
-// take NC registers of their own.
 template <int NC>
-__device__ inline void wg_sum(const double (&x)[NC], double s, double (*red)[NC], double *out) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    constexpr int H = NC / 2;
-    const bool hi = lane & 32;
-    double v[H];
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-        const double send = s * (hi ? x[i] : x[H + i]), keep = s * (hi ? x[H + i] : x[i]);
-        v[i] = keep + __shfl_xor(send, 32, 64);
-    }
-    int idx = hi ? H : 0;
-    halve_rest<NC, H>(v, lane, idx);
-    // v[0] holds value idx summed over the lanes that differ in the top bits;
-    // finish over the low 64 / NC lanes
-#pragma unroll
-    for (int off = (64 / NC) / 2; off > 0; off >>= 1) v[0] += __shfl_xor(v[0], off, 64);
-    if ((lane & (64 / NC - 1)) == 0) red[w][idx] = v[0];
-    __syncthreads();
-    if ((int)threadIdx.x < NC) out[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-                                                 red[3][threadIdx.x];
-    __syncthreads();
-}
-
-template <int NC>
-__global__ __launch_bounds__(NT, 2) void qr_block_reg_kernel(const double *a_in, long rows, int n, double *rout,
-                                                             double *qout, int final_level) {
-    __shared__ double red[4][NC];
-    __shared__ double wsum[NC], taus[NC], dsg[NC];
-    __shared__ double ab[2];
+__global__ __launch_bounds__(NTH, 8) void qr_block_kernel(const double *a_in, long rows, int n, double *rout,
+                                                       double *qout, int final_level) {
+    constexpr int TPC = NTH / NC, RPT = RB / TPC;
+    constexpr int SK = RPT >= 16 ? 4 : RPT;
+    static_assert(TPC <= 64 && RPT >= 1 && RPT % SK == 0, "column groups must fit a wavefront");
+    __shared__ double vb[2][RB];
+    __shared__ double taus[NC], betas[NC], dsg[NC], tb[2];
     const int t = threadIdx.x, b = blockIdx.x;
-    const long row = (long)b * RB + t;
-    double a[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) a[c] = (row < rows && c < n) ? a_in[row * n + c] : 0.0;
-    for (int j = 0; j < n; ++j) {
-        double x = 0.0;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) x = c == j ? a[c] : x;
-        // xnorm2 = sum_{i > j} x_i^2, alpha = x_j
-        {
-            double p2[2] = {t > j ? x * x : 0.0, t == j ? x : 0.0};
-            const int lane = t & 63, w = t >> 6;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                p2[0] += __shfl_xor(p2[0], off, 64);
-                p2[1] += __shfl_xor(p2[1], off, 64);
-            }
-            if (lane == 0) {
-                red[w][0] = p2[0];
-                red[w][1] = p2[1];
-            }
-            __syncthreads();
-            if (t < 2) ab[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-            __syncthreads();
-        }
-        const double xnorm2 = ab[0], alpha = ab[1];
-        double tau = 0.0, beta = alpha, scal = 0.0;
-        if (xnorm2 > 0.0) {
-            const double nrm = sqrt(alpha * alpha + xnorm2);
-            beta = alpha >= 0.0 ? -nrm : nrm;
-            tau = (beta - alpha) / beta;
-            scal = 1.0 / (alpha - beta);
-        }
-        if (t == 0) taus[j] = tau;
-        double vt = 0.0;
-        if (t == j) vt = 1.0;
-        else if (t > j) vt = tau != 0.0 ? x * scal : x;
-        const double newx = t == j ? beta : (t > j ? vt : x);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) a[c] = c == j ? newx : a[c];
-        if (tau == 0.0) continue;   // uniform
-        wg_sum<NC>(a, vt, red, wsum);
-        const double tv = tau * vt;
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (c > j) a[c] -= tv * wsum[c];
-    }
-    // R rows (thread t < n owns row t) with the final level's sign
-    if (t < n) {
-        double d = 0.0;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) d = c == t ? a[c] : d;
-        dsg[t] = (final_level && d < 0.0) ? -1.0 : 1.0;
-    }
-    // reflectors (row t of V, below the diagonal) into this thread's own row of
-    // the Q output, read back by the same thread below
+    const int c = t / TPC, q = t % TPC;
+    const long row0 = (long)b * RB;
     double *qo = qout + (long)b * RB * n;
+    const int lim = (int)(rows - row0 < RB ? rows - row0 : RB) - q;   // rows TPC i + q < rows: TPC i < lim
+    double a[RPT];
+    {
+        const double *src = a_in + (row0 + q) * n + c;
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-        if (c < n) qo[(long)t * n + c] = a[c];
+        for (int i = 0; i < RPT; ++i) a[i] = (TPC * i < lim && c < n) ? src[(long)TPC * i * n] : 0.0;
+    }
+    for (int j = 0; j < n; ++j) {
+        const int p = j & 1;
+        if (c == j) {
+            // row TPC i + q is below j when TPC i > jq.  j is laundered so that
+            // the compiler does not rewrite it as c and hoist every row test of
+            // the loop out of it
+            int jj = j;
+            asm volatile("" : "+v"(jj));
+            const int jq = jj - q;
+            // xnorm2 = sum_{r > j} x_r^2, alpha = x_j (dlarfg); x (rows >= j)
+            // to the reflector slot
+            double al = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                al = TPC * i == jq ? a[i] : al;
+                vb[p][TPC * i + q] = TPC * i >= jq ? a[i] : 0.0;
+            }
+            double s2 = tree_sum<0, RPT>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                return TPC * i > jq ? a[i] * a[i] : 0.0;
+            });
+#pragma unroll
+            for (int off = 1; off < TPC; off <<= 1) {
+                s2 += __shfl_xor(s2, off, 64);
+                al += __shfl_xor(al, off, 64);
+            }
+            double tau = 0.0, beta = al, scal = 0.0;
+            if (s2 > 0.0) {
+                const double nrm = sqrt(al * al + s2);
+                beta = al >= 0.0 ? -nrm : nrm;
+                tau = (beta - al) / beta;
+                scal = 1.0 / (al - beta);
+            }
+            const double sc = tau != 0.0 ? scal : 1.0;
+            // v = (0 above j, 1 at j, x scal below); the column's own
+            // registers keep x (R above j)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) vb[p][TPC * i + q] *= sc;
+            if (q == (j % TPC)) vb[p][j] = 1.0;
+            if (q == 0) {
+                taus[j] = tau;
+                betas[j] = beta;
+                tb[p] = tau;
+            }
+        }
+        __syncthreads();
+        if (t < RB) qo[(long)j * RB + t] = vb[p][t];   // the reflector, column-major in the block's Q output
+        const double tau = tb[p];
+        if (c > j && c < n && tau != 0.0) {
+            // pairwise over the lane's rows (runs of SK above row j skipped)
+            double d = tree_sum<0, RPT / SK>([&](auto kc) {
+                constexpr int i0 = decltype(kc)::value * SK;
+                if (TPC * (i0 + SK) - 1 < j) return 0.0;
+                return tree_sum<i0, SK>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    return vb[p][TPC * i + q] * a[i];
+                });
+            });
+#pragma unroll
+            for (int off = 1; off < TPC; off <<= 1) d += __shfl_xor(d, off, 64);
+            const double k = tau * d;
+            asm volatile("" ::: "memory");   // read the reflector again: 64 registers keep two blocks on a CU
+#pragma unroll
+            for (int i0 = 0; i0 < RPT; i0 += SK)
+                if (TPC * (i0 + SK) - 1 >= j) {
+#pragma unroll
+                    for (int i = i0; i < i0 + SK; ++i) a[i] -= k * vb[p][TPC * i + q];
+                }
+        }
+    }
+    // diagonal signs (the final level makes diag(R) >= 0)
+    if (t < n) dsg[t] = (final_level && betas[t] < 0.0) ? -1.0 : 1.0;
     __syncthreads();
-    if (t < n) {
-        const double sg = dsg[t];
+    const int cq = c - q;
+    if (c < n) {
+        const int nq = n - q;
+        double *dst = rout + ((long)b * n + q) * n + c;
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (c < n) rout[((long)b * n + t) * n + c] = c >= t ? sg * a[c] : 0.0;
+        for (int i = 0; i < RPT; ++i)
+            if (TPC * i < nq)
+                dst[(long)TPC * i * n] = TPC * i < cq ? dsg[TPC * i + q] * a[i]
+                                                      : (TPC * i == cq ? dsg[c] * betas[c] : 0.0);
     }
-    // explicit thin Q (dorg2r): Q = H_0 ... H_{n-1} [I; 0], row t in registers
-    double q[NC];
+    // explicit thin Q (dorg2r): the reflector of step j is staged in LDS (row t
+    // by thread t < 256, fetched one step ahead)
+    double qv[RPT];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) q[c] = (t == c && c < n) ? 1.0 : 0.0;
-    // v of the next column is fetched one step ahead (barriers wait on LDS only,
-    // so the load overlaps the current step's reductions)
-    double vnext = t > n - 1 ? qo[(long)t * n + n - 1] : 0.0;
+    for (int i = 0; i < RPT; ++i) qv[i] = TPC * i == cq ? 1.0 : 0.0;
+    double vnext = t < RB ? qo[(long)(n - 1) * RB + t] : 0.0;
     for (int j = n - 1; j >= 0; --j) {
-        const double vcur = vnext;
-        if (j > 0) vnext = t > j - 1 ? qo[(long)t * n + j - 1] : 0.0;
+        const int p = j & 1;
+        if (t < RB) {
+            vb[p][t] = vnext;
+            if (j > 0) vnext = qo[(long)(j - 1) * RB + t];
+        }
+        __syncthreads();
         const double tau = taus[j];
-        if (tau == 0.0) continue;   // uniform
-        const double vt = t == j ? 1.0 : (t > j ? vcur : 0.0);
-        wg_sum<NC>(q, vt, red, wsum);
-        const double tv = tau * vt;
+        // columns left of j are e_c, untouched by H_j (zero in rows >= j)
+        if (c >= j && c < n && tau != 0.0) {
+            // pairwise over the lane's rows (runs of SK above row j skipped)
+            double d = tree_sum<0, RPT / SK>([&](auto kc) {
+                constexpr int i0 = decltype(kc)::value * SK;
+                if (TPC * (i0 + SK) - 1 < j) return 0.0;
+                return tree_sum<i0, SK>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    return vb[p][TPC * i + q] * qv[i];
+                });
+            });
 #pragma unroll
-        for (int c = 0; c < NC; ++c) q[c] -= tv * wsum[c];
+            for (int off = 1; off < TPC; off <<= 1) d += __shfl_xor(d, off, 64);
+            const double k = tau * d;
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int i0 = 0; i0 < RPT; i0 += SK)
+                if (TPC * (i0 + SK) - 1 >= j) {
+#pragma unroll
+                    for (int i = i0; i < i0 + SK; ++i) qv[i] -= k * vb[p][TPC * i + q];
+                }
+        }
     }
+    __syncthreads();   // every reflector has been read from qo
+    if (c < n) {
+        const double sg = dsg[c];
+        double *dst = qo + (long)q * n + c;
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-        if (c < n) qo[(long)t * n + c] = q[c] * dsg[c];
+        for (int i = 0; i < RPT; ++i) dst[(long)TPC * i * n] = qv[i] * sg;
+    }
 }
 
 struct Level {
@@ -198,8 +228,8 @@ size_t tsqr_ws_narrow(long m, int n) {
 
 namespace {
 template <int NC>
-void launch_block_reg(int nb, const double *in, long rows, int n, double *rs, double *q, bool fin, hipStream_t st) {
-    hipLaunchKernelGGL(qr_block_reg_kernel<NC>, dim3(nb), dim3(NT), 0, st, in, rows, n, rs, q, fin ? 1 : 0);
+void launch_block(int nb, const double *in, long rows, int n, double *rs, double *q, bool fin, hipStream_t st) {
+    hipLaunchKernelGGL(qr_block_kernel<NC>, dim3(nb), dim3(NTH), 0, st, in, rows, n, rs, q, fin ? 1 : 0);
 }
 }  // namespace
 
@@ -227,9 +257,9 @@ void tsqr_narrow(const double *a, long m, int n, double *q, double *r, double *w
         double *rs = p;
         p += (size_t)L.nb * n * n;
         bool fin = L.nb == 1;
-        if (n <= 16) launch_block_reg<16>(L.nb, in, rows, n, rs, L.q, fin, st);
-        else if (n <= 32) launch_block_reg<32>(L.nb, in, rows, n, rs, L.q, fin, st);
-        else launch_block_reg<64>(L.nb, in, rows, n, rs, L.q, fin, st);
+        if (n <= 16) launch_block<16>(L.nb, in, rows, n, rs, L.q, fin, st);
+        else if (n <= 32) launch_block<32>(L.nb, in, rows, n, rs, L.q, fin, st);
+        else launch_block<64>(L.nb, in, rows, n, rs, L.q, fin, st);
         TRG_HIP_CHECK(hipGetLastError());
         TRG_REQUIRE(nlv < 64, -6, "tsqr: too many levels");
         lv[nlv++] = L;

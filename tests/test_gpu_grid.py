@@ -2,9 +2,17 @@
 
 beta in {0.140, 0.1497, 0.160} x h in {0, 1e-4}, 80 steps (L = 2^20 per axis),
 r = 7, sketch width 2D, one power iteration; the oracle's flows are written by
-tests/golden/make_golden.py.  After every step the FP64 GPU path must give:
+tests/golden/make_golden.py.  The FP64 GPU path must give:
 
-* log Z/V within 1e-10 relative (the FP64 parity target);
+* the free energy, log Z/V after the last step (L = 2^20), within 1e-10
+  relative (the FP64 parity target), and log Z/V after every earlier step
+  within 3e-10.  The finite-volume values of the first steps carry the
+  flow's own rounding sensitivity: the oracle run again with only the row
+  order of its QR inputs permuted (the same factorisation, other rounding)
+  differs from its stored flow by 1.07e-10 at step 4 of beta = 0.140,
+  h = 1e-4 (4.1e-12 at step 2, 1.8e-11 at step 6, 1e-13 from step 5 on
+  otherwise), so a per-step bound of 1e-10 there would fail the oracle
+  against itself;
 * the same kept bond count, and the kept bond-swap singular values and the
   re-split spectrum s / c_k within 2e-7 of the largest value.  The bond
   values come from the randomized SVD: its sketch (M M^T) M Omega has a
@@ -57,7 +65,8 @@ def _golden(name):
     return g
 
 
-def run_against(g, precision=trg.FP64, tol_f=1e-10, tol_s=2e-7, spectra=True, max_degenerate=1, spectra_steps=20):
+def run_against(g, precision=trg.FP64, tol_f=1e-10, tol_s=2e-7, spectra=True, max_degenerate=1, spectra_steps=20,
+                tol_step=3e-10):
     c = g["params"]
     s = trg.Solver(seed=c["seed"], precision=precision, tau_deg=c.get("tau_deg", 0.0),
                    r_bond=c.get("r_bond", 1), sketch_mult=c.get("sketch_mult", 2))
@@ -70,6 +79,7 @@ def run_against(g, precision=trg.FP64, tol_f=1e-10, tol_s=2e-7, spectra=True, ma
         f = s.log_z_per_site()
         rel = abs(f - ref) / abs(ref)
         worst_f = max(worst_f, rel)
+        assert rel <= max(tol_step, tol_f), (i, rel)
         if spectra and ndeg == 0 and i < spectra_steps:
             sp = g["spectra"][i]
             sig = s.export(trg.T_SIGMA)
@@ -98,7 +108,7 @@ def run_against(g, precision=trg.FP64, tol_f=1e-10, tol_s=2e-7, spectra=True, ma
     if spectra:
         _say("  largest spectral difference at " + where)
         assert ndeg <= max_degenerate, ndeg
-    assert worst_f <= tol_f, worst_f
+    assert rel <= tol_f, ("free energy after the last step", rel)
     assert worst_s <= tol_s, worst_s
     return worst_f, worst_s
 
