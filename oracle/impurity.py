@@ -36,7 +36,12 @@ Readings (the paper gives no formulas for this part):
   subspace moves with the Gram (eq. HOSVD): dU = W C, W the discarded
   eigenvectors and C[j, i] = w_j^T dG u_i / (lam_i - lam_j) (first-order
   perturbation of an invariant subspace), with dG the Gram's tangent from
-  dA, d(X sigma), dY, dD.  Holding U instead (iso=False) gives the
+  dA, d(X sigma), dY, dD.  Pairs with lam_i - lam_j <= 1e-12 lam_1 are left
+  out (C = 0): eigen-directions whose eigenvalues lie that close are not
+  determined by the Gram (at D = 8, h = 0 the kept/discarded cut falls
+  between eigenvalues of 1.2e-14 and 6.6e-15 of the largest, within a few
+  rounding errors eps lam_1 of each other), so the rotation between them
+  has no derivative; the pair is treated as degenerate, as a multiplet.  Holding U instead (iso=False) gives the
   derivative of the flow with its isometries frozen, which near T_c differs
   from the flow's own derivative by 10 % or more; the squeezers are held
   (freezing them moves the derivative by about 1e-3 at D = 8);
@@ -175,6 +180,9 @@ def _gram_tangents(a, x, sig, y, dt, da, dxs, dy, ddm):
     return [g.reshape(nn, nn) for g in (dga, dgx, dgy, dgd)]
 
 
+ISO_GAP = 1e-12   # eigenvalue gaps (relative to the largest) below which a pair has no derivative
+
+
 def _iso_tangent(gram, dgram, d1, d2, cap, prm):
     """dU of a truncated HOSVD isometry (trg.triad_isometry) along dgram, [d1, d2, cap]."""
     n = d1 * d2
@@ -184,7 +192,9 @@ def _iso_tangent(gram, dgram, d1, d2, cap, prm):
     kept = trg.kept_count(lam, cap, prm.eps_lam, prm.tau_deg)
     u, wd = w[:, :kept], w[:, kept:]
     sg = trg.fix_signs(u, (d1, d2))
-    cm = (wd.T @ dgram @ u) / (lam[None, :kept] - lam[kept:, None])
+    gap = lam[None, :kept] - lam[kept:, None]
+    ok = gap > ISO_GAP * lam[0]
+    cm = np.where(ok, wd.T @ dgram @ u, 0.0) / np.where(ok, gap, 1.0)
     out = np.zeros((n, cap))
     out[:, :kept] = (wd @ cm) * sg
     return out.reshape(d1, d2, cap)

@@ -1083,30 +1083,39 @@ void axpy_scale(Ctx &c, DT &y, const DT *x, double a, const double *cdev) {
     TRG_HIP_CHECK(hipGetLastError());
 }
 
+// Eigenvalue gap, relative to the largest, at or below which a kept /
+// discarded pair gets no derivative: eigen-directions that close are not
+// determined by the Gram (the cut can fall between eigenvalues a few rounding
+// errors of the largest apart), so the pair is treated as degenerate
+constexpr double ISO_GAP = 1e-12;
+
 // C[j, i] (n x cap) = P[j, i] / (lam_i - lam_j) for a kept i < *kept and a
-// discarded j >= *kept, else 0
+// discarded j >= *kept whose gap exceeds ISO_GAP lam_0, else 0
 __global__ void iso_coef_kernel(const double *P, const double *lam, const int *kept, int n, int cap, double *C) {
     const long tot = (long)n * cap;
     const int k = *kept;
+    const double cut = ISO_GAP * lam[0];
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
         const int j = (int)(e / cap), i = (int)(e - (long)j * cap);
         double v = 0.0;
         if (i < k && j >= k) {
             const double den = lam[i] - lam[j];
-            v = den != 0.0 ? P[(long)j * n + i] / den : 0.0;
+            v = den > cut ? P[(long)j * n + i] / den : 0.0;
         }
         C[e] = v;
     }
 }
 
-// out[p, i] = vec[p, i] / lam[i] for the kept i < *kept, else 0 (n x cap)
+// out[p, i] = vec[p, i] / lam[i] for the kept i < *kept whose eigenvalue
+// exceeds ISO_GAP lam_0 (its gap to the null space), else 0 (n x cap)
 __global__ void kept_over_lam_kernel(const double *vec, const double *lam, const int *kept, int n, int cap,
                                      double *out) {
     const long tot = (long)n * cap;
     const int k = *kept;
+    const double cut = ISO_GAP * lam[0];
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
         const int p = (int)(e / cap), i = (int)(e - (long)p * cap);
-        out[e] = (i < k && lam[i] != 0.0) ? vec[(long)p * n + i] / lam[i] : 0.0;
+        out[e] = (i < k && lam[i] > cut) ? vec[(long)p * n + i] / lam[i] : 0.0;
     }
 }
 

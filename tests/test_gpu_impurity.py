@@ -3,18 +3,15 @@
 d(log Z/V)/d(beta) and d(log Z/V)/dh after every step.  Exact tori: the
 untruncated first steps must equal the enumerated Boltzmann averages to
 1e-12.  Flows: log Z/V at 1e-10 relative after every step; the derivatives at
-1e-6 relative (d/dh, which passes through zero at h = 0, relative to
-1e-3 |d/dbeta| at least), 5e-6 for the D = 8, h = 0 flow.  The re-split
-tangent multiplies by S'^+ (1/s on values down to 1e-14 of the largest), and
-the rounding noise that each side carries in the small-s directions of the
-bond-swap factors and in the eigenvectors of the rank-deficient triad Grams
-is amplified there; where the spectra are well separated the two sides agree
-to 1e-11.  The D = 8, h = 0 flow (whose spin-flip symmetry the sketch
-breaks) is the sensitive one: the oracle's own tangent moves by 2e-7 from
-step 3 on when its Jacobi eigensolver is replaced by LAPACK's, and the GPU's
-(pivoted Cholesky and one-sided Jacobi) by up to 3.5e-6 when only the
-summation order inside its QR changes (7e-7, 3.0e-6 and 3.5e-6 for three
-orders).
+1e-7 relative (d/dh, which passes through zero at h = 0, relative to
+1e-3 |d/dbeta| at least); measured 3.9e-12 (D = 6, h = 1e-3), 2.9e-9
+(D = 8, h = 0), 5.6e-10 (D = 6, beta = 0.3) and 4.3e-9 (D = 16, h = 1e-4).
+Both sides leave out of the isometry derivative the kept / discarded
+eigenvalue pairs closer than 1e-12 of the largest: at D = 8, h = 0 the cut
+falls between Gram eigenvalues of 1.2e-14 and 6.6e-15 of the largest, whose
+eigenvectors the Gram does not determine, and with those pairs in, the two
+eigen-routes (pivoted Cholesky with one-sided Jacobi here, two-sided Jacobi
+in the oracle) gave derivatives 1e-6 to 4e-6 apart.
 """
 import math
 import sys
@@ -27,7 +24,7 @@ from oracle import trg as otrg, impurity
 from oracle.ising import enumerate_derivatives_per_site
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-6
+TOL = 1e-7
 
 
 def _say(*a):
@@ -60,9 +57,9 @@ def test_beta_zero_magnetisation():
         assert math.isnan(db) and abs(dh - math.tanh(0.3)) < 1e-14
 
 
-@pytest.mark.parametrize("D,nsteps,beta,h,tol", [(6, 12, 0.1497, 1e-3, TOL), (8, 10, 0.1497, 0.0, 5e-6),
-                                                 (6, 10, 0.3, 0.0, TOL), (16, 6, 0.1497, 1e-4, TOL)])
-def test_matches_oracle_every_step(D, nsteps, beta, h, tol):
+@pytest.mark.parametrize("D,nsteps,beta,h", [(6, 12, 0.1497, 1e-3), (8, 10, 0.1497, 0.0), (6, 10, 0.3, 0.0),
+                                             (16, 6, 0.1497, 1e-4)])
+def test_matches_oracle_every_step(D, nsteps, beta, h):
     _say("impurity vs oracle D=%d beta=%g h=%g" % (D, beta, h))
     prm = otrg.Params(D=D, seed=29)
     ist = impurity.ImpurityState(beta, h, 4)
@@ -80,7 +77,8 @@ def test_matches_oracle_every_step(D, nsteps, beta, h, tol):
         eh = abs(gh - oh) / max(abs(oh), 1e-3 * abs(ob))
         worst = max(worst, eb, eh)
         _say("  step %2d  d/dbeta gpu %.15f oracle %.15f   d/dh gpu %.3e oracle %.3e" % (i, gb, ob, gh, oh))
-    assert worst <= tol, worst
+    _say("  worst %.2e" % worst)
+    assert worst <= TOL, worst
 
 
 def test_errors():
