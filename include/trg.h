@@ -343,9 +343,15 @@ const char *trg_last_error(trg_state *s);
 int trg_selftest_gemm(int precision, int ta, int tb, int M, int N, int K, int batch,
                       const double *A, const double *B, double *C);
 
-/* Thin QR of A (m x n, m >= n, n <= 64) by the register-resident Householder TSQR:
- * Q (m x n), R (n x n) with diag(R) >= 0. */
+/* Thin QR of A (m x n, m >= n; n <= 512) by the Householder TSQR (n > 64:
+ * blocked over 64-column panels): Q (m x n), R (n x n) with diag(R) >= 0. */
 int trg_selftest_tsqr(int m, int n, const double *A, double *Q, double *R);
+
+/* dst = src with its axes permuted, as the contractions reshape tensor legs
+ * between GEMMs: src has nd <= 8 axes of sizes dims[0..nd) (row-major), dst
+ * axis i is src axis perm[i] (row-major, the same number of elements).
+ * TRG_E_INVALID if perm is not a permutation of 0..nd-1 or a size is < 1. */
+int trg_selftest_permute(int nd, const int *dims, const int *perm, const double *src, double *dst);
 
 /* One-sided Jacobi SVD of A (m x n, m >= n): U (m x n), s (n) descending,
  * V (n x n).  Returns the number of sweeps in *sweeps. */

@@ -90,6 +90,8 @@ def load_library(path=None):
     lib.trg_last_error.restype = ctypes.c_char_p
     lib.trg_selftest_gemm.argtypes = [ctypes.c_int] * 7 + [_DP, _DP, _DP]
     lib.trg_selftest_tsqr.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP]
+    _IP = ctypes.POINTER(ctypes.c_int)
+    lib.trg_selftest_permute.argtypes = [ctypes.c_int, _IP, _IP, _DP, _DP]
     lib.trg_selftest_svd.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP, _DP, ctypes.POINTER(ctypes.c_int)]
     lib.trg_selftest_eigh.argtypes = [ctypes.c_int, ctypes.c_int, _DP, _DP, _DP, ctypes.POINTER(ctypes.c_int)]
     lib.trg_selftest_pchol.argtypes = [ctypes.c_int, ctypes.c_int, _DP, ctypes.c_double, _DP,
@@ -124,7 +126,7 @@ def load_library(path=None):
               "impurity_derivatives",
               "trg_shape", "trg_export", "trg_set_timing", "trg_kernel_time", "trg_selftest_gemm",
               "trg_selftest_tsqr", "trg_selftest_svd", "trg_selftest_eigh", "trg_selftest_pchol",
-              "trg_selftest_gram_eig", "trg_selftest_sketch"):
+              "trg_selftest_gram_eig", "trg_selftest_sketch", "trg_selftest_permute"):
         getattr(lib, f).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -322,6 +324,18 @@ def selftest_gemm(a, b, ta=False, tb=False, precision=FP64):
     c = np.empty((batch, m, n))
     _check(lib.trg_selftest_gemm(precision, int(ta), int(tb), m, n, k, batch, _p(a), _p(b), _p(c)))
     return c
+
+
+def selftest_permute(a, perm):
+    """np.transpose(a, perm) computed by the library's permute."""
+    lib = load_library()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    nd = a.ndim
+    dims = (ctypes.c_int * nd)(*a.shape)
+    pm = (ctypes.c_int * nd)(*perm)
+    out = np.empty(a.size)
+    _check(lib.trg_selftest_permute(nd, dims, pm, _p(a), _p(out)))
+    return out.reshape(tuple(a.shape[p] for p in perm))
 
 
 def selftest_tsqr(a):

@@ -2282,6 +2282,27 @@ int trg_selftest_gemm(int precision, int ta, int tb, int M, int N, int K, int ba
     return TRG_OK;
 }
 
+int trg_selftest_permute(int nd, const int *dims, const int *perm, const double *src, double *dst) {
+    if (!dims || !perm || !src || !dst || nd < 1 || nd > 8) return TRG_E_INVALID;
+    std::vector<int> dv(dims, dims + nd), pv(perm, perm + nd), seen(nd, 0);
+    size_t total = 1;
+    for (int i = 0; i < nd; ++i) {
+        if (dv[i] < 1 || pv[i] < 0 || pv[i] >= nd || seen[pv[i]]++) return TRG_E_INVALID;
+        total *= (size_t)dv[i];
+    }
+    try {
+        Scratch s;
+        double *a = s.up(src, total);
+        double *b = s.ar.dalloc(total);
+        trg::permute(a, b, dv, pv, nullptr);
+        s.down(dst, b, total);
+    } catch (const Error &e) {
+        g_err = e.what();
+        return e.code;
+    }
+    return TRG_OK;
+}
+
 int trg_selftest_tsqr(int m, int n, const double *A, double *Q, double *R) {
     if (!A || !Q || !R || n < 1 || m < n) return TRG_E_INVALID;
     try {

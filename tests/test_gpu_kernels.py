@@ -33,6 +33,28 @@ def test_gemm_f64(shape, ta, tb):
     assert np.max(np.abs(c - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))) * np.sqrt(k)
 
 
+# every path of the library's permute: two contiguous groups swapped (tiled
+# transpose), the source's unit-stride axis moved (tiled through LDS), the
+# unit-stride axis kept last (a wavefront per row; ragged and long rows), and
+# the element-wise fallback (short last axis)
+@pytest.mark.parametrize("shape,perm", [((3, 40, 70), (0, 2, 1)), ((17, 5, 33, 40), (3, 1, 0, 2)),
+                                        ((6, 7, 9, 64), (2, 0, 1, 3)), ((5, 3, 11, 13), (1, 2, 0, 3)),
+                                        ((64, 32, 32, 64), (1, 0, 2, 3)), ((4, 5, 6, 3), (2, 1, 0, 3)),
+                                        ((2, 1, 3, 1, 200), (4, 2, 0, 1, 3)), ((7,), (0,))])
+def test_permute_exact(shape, perm):
+    _say("permute", shape, perm)
+    a = np.random.default_rng(len(shape) * 100 + shape[0]).standard_normal(shape)
+    assert np.array_equal(trg.selftest_permute(a, perm), np.transpose(a, perm))
+
+
+def test_permute_rejects_bad_permutations():
+    a = np.zeros((2, 3))
+    for perm in [(0, 0), (0, 2)]:
+        with pytest.raises(trg.TrgError) as e:
+            trg.selftest_permute(a, perm)
+        assert e.value.code == -1
+
+
 @pytest.mark.parametrize("m,n", [(4, 4), (37, 5), (256, 64), (1000, 33), (5000, 64), (70000, 17), (300000, 2),
                                  (64, 64), (257, 40), (100003, 64)])
 def test_tsqr(m, n):
