@@ -34,9 +34,9 @@ def test_gemm_f64(shape, ta, tb):
 
 
 # every path of the library's permute: two contiguous groups swapped (tiled
-# transpose), the source's unit-stride axis moved (tiled through LDS), the
-# unit-stride axis kept last (a wavefront per row; ragged and long rows), and
-# the element-wise fallback (short last axis)
+# transpose), the source's unit-stride axis moved (tiled through LDS), and the
+# element-wise kernel (the unit-stride axis kept last, with short, ragged and
+# long rows, or a short destination row); a single axis is a copy
 @pytest.mark.parametrize("shape,perm", [((3, 40, 70), (0, 2, 1)), ((17, 5, 33, 40), (3, 1, 0, 2)),
                                         ((6, 7, 9, 64), (2, 0, 1, 3)), ((5, 3, 11, 13), (1, 2, 0, 3)),
                                         ((64, 32, 32, 64), (1, 0, 2, 3)), ((4, 5, 6, 3), (2, 1, 0, 3)),
