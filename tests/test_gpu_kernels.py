@@ -35,9 +35,12 @@ def test_gemm_f64(shape, ta, tb):
 
 # every path of the library's permute: two contiguous groups swapped (tiled
 # transpose), the source's unit-stride axis moved (tiled through LDS), and the
-# element-wise kernel (the unit-stride axis kept last, with short, ragged and
-# long rows, or a short destination row); a single axis is a copy
+# element-wise kernel (the unit-stride axis kept last with the other axes
+# reordered, as in the step's 32^5 tensors, with short, ragged and long rows,
+# or a short destination row); a single axis is a copy
 @pytest.mark.parametrize("shape,perm", [((3, 40, 70), (0, 2, 1)), ((17, 5, 33, 40), (3, 1, 0, 2)),
+                                        ((16, 16, 16, 16, 32), (1, 2, 3, 0, 4)), ((5, 9, 11, 13, 24), (3, 0, 1, 2, 4)),
+                                        ((32, 10, 20, 16), (2, 0, 1, 3)), ((9, 8, 64), (1, 0, 2)),
                                         ((6, 7, 9, 64), (2, 0, 1, 3)), ((5, 3, 11, 13), (1, 2, 0, 3)),
                                         ((64, 32, 32, 64), (1, 0, 2, 3)), ((4, 5, 6, 3), (2, 1, 0, 3)),
                                         ((2, 1, 3, 1, 200), (4, 2, 0, 1, 3)), ((7,), (0,))])
