@@ -270,22 +270,41 @@ void tsqr_narrow(const double *a, long m, int n, double *q, double *r, double *w
         in = rs;
         rows = (long)L.nb * n;
     }
-    // rebuild Q top-down
+    // rebuild Q top-down; the first level's product goes straight into q (its
+    // blocks that lie inside q in one batch, a last block that runs past row
+    // m on its own)
     long nb0 = lv[0].nb;
     double *bufA = p, *bufB = p + (size_t)nb0 * BR * n;
     const double *upper = lv[nlv - 1].q;   // rows_L x n (padded to BR)
     for (int l = nlv - 2; l >= 0; --l) {
-        double *dst = (l % 2 == 0) ? bufA : bufB;
+        double *dst = l == 0 ? q : ((l % 2 == 0) ? bufA : bufB);
         GemmArgs g{};
         g.M = BR; g.N = n; g.K = n; g.batch = lv[l].nb;
         g.A = lv[l].q; g.sAr = n; g.sAk = 1; g.sAb = (long)BR * n;
         g.B = upper; g.sBk = n; g.sBn = 1; g.sBb = (long)n * n;
         g.C = dst; g.sCr = n; g.sCn = 1; g.sCb = (long)BR * n;
         g.alpha = 1.0; g.beta = 0.0;
-        gemm(g, P_FP64, st);
+        if (l > 0) {
+            gemm(g, P_FP64, st);
+        } else {
+            const long full = m / BR;
+            const int rem = (int)(m - full * BR);
+            if (full > 0) {
+                g.batch = (int)full;
+                gemm(g, P_FP64, st);
+            }
+            if (rem > 0) {
+                GemmArgs h = g;
+                h.M = rem; h.batch = 1;
+                h.A = lv[0].q + full * BR * n;
+                h.B = upper + full * n * n;
+                h.C = q + full * BR * n;
+                gemm(h, P_FP64, st);
+            }
+        }
         upper = dst;
     }
-    copy(q, upper, (size_t)m * n, st);
+    if (nlv == 1) copy(q, upper, (size_t)m * n, st);
 }
 
 
