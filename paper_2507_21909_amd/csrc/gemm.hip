@@ -381,6 +381,24 @@ int tuned_gm(const std::array<long, 8> &key, hipStream_t st, bool eligible, cons
 
 void gemm_f64(const GemmArgs &g, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+    // a ragged last column tile keeps the whole launch off the vector kernel:
+    // the 64-aligned columns go to it and the rest to the general kernel (each
+    // element of C sums its K terms in the same MFMA order in both, so the
+    // split changes no bits)
+    if (!ev0 && g.N > 64 && g.N % 64 != 0 && g.cN2 == 0) {
+        GemmArgs h = g;
+        h.N = g.N - g.N % 64;
+        bool ak1 = false, bn1 = false;
+        if (vec_ok(h, &ak1, &bn1)) {
+            gemm_f64(h, st, nullptr, nullptr);
+            GemmArgs r = g;
+            r.N = g.N % 64;
+            r.B = g.B + (long)h.N * g.sBn;
+            r.C = g.C + (long)h.N * g.sCn;
+            gemm_f64(r, st, nullptr, nullptr);
+            return;
+        }
+    }
     const int inner = std::max(1, g.inner);
     // shapes of every launch on stderr when TRG_GEMM_TRACE is set
     static const bool trace = [] {

@@ -16,9 +16,12 @@ def _say(*a):
 
 
 # (5, 64, 64, 64), (2, 128, 192, 64), (1, 256, 64, 1024): every tile inside C and
-# K a multiple of 32, the vector-load kernel; the others the general one
+# K a multiple of 32, the vector-load kernel; (2, 128, 224, 64): its first 192
+# columns on the vector kernel, the last 32 on the general one; the others the
+# general one
 @pytest.mark.parametrize("shape", [(1, 16, 16, 4), (3, 67, 45, 33), (2, 130, 70, 129), (1, 1, 200, 17),
-                                   (5, 64, 64, 64), (1, 300, 1, 7), (2, 128, 192, 64), (1, 256, 64, 1024), (1, 64, 128, 48)])
+                                   (5, 64, 64, 64), (1, 300, 1, 7), (2, 128, 192, 64), (1, 256, 64, 1024), (1, 64, 128, 48),
+                                   (2, 128, 224, 64)])
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
 def test_gemm_f64(shape, ta, tb):
     batch, m, n, k = shape
