@@ -18,6 +18,11 @@
   against a central difference); holding the isometries instead reproduces
   the central difference of the flow with its isometries and squeezers
   frozen (9e-4), 12 % away from the flow's derivative.
+* The isometry derivative alone: on a Gram with separated eigenvalues the
+  projector's first-order change (dU U^T + U dU^T) equals a central
+  difference of the exact eigen-decomposition; a kept / discarded pair
+  closer than 1e-12 of the largest eigenvalue gets no rotation, the other
+  pairs the textbook coefficient w_j^T dG u_i / (lam_i - lam_j).
 """
 import math
 
@@ -142,3 +147,54 @@ def test_four_dimensional_near_tc_isometry_derivative(monkeypatch):
     # the isometries' share of the derivative is not small here: the pin above
     # would fail with the isometries held
     assert abs(u_frozen - u_free) > 0.05 * abs(u_free)
+
+
+def _gram(lam, seed):
+    rng = np.random.default_rng(seed)
+    w, _ = np.linalg.qr(rng.standard_normal((len(lam), len(lam))))
+    return (w * np.asarray(lam)[None, :]) @ w.T, w
+
+
+def _projector(g, kept):
+    lam, w = np.linalg.eigh(g)
+    u = w[:, np.argsort(lam)[::-1][:kept]]
+    return u @ u.T
+
+
+def test_isometry_derivative_is_the_projector_derivative():
+    d1, d2, cap = 3, 4, 5
+    lam = [3.0, 2.2, 1.7, 1.1, 0.8, 0.31, 0.2, 0.12, 0.05, 0.02, 0.0, 0.0]   # rank 10, gap at the cut
+    g, _ = _gram(lam, 4)
+    rng = np.random.default_rng(5)
+    dg = rng.standard_normal((12, 12))
+    dg = dg + dg.T
+    prm = trg.Params(D=cap, tau_deg=0.0)
+    u = trg.triad_isometry(g, d1, d2, cap, prm, "t", {})
+    du = impurity._iso_tangent(g, dg, d1, d2, cap, prm).reshape(12, cap)
+    dp = du @ u.T + u @ du.T
+    eps = 1e-5
+    fd = (_projector(g + eps * dg, cap) - _projector(g - eps * dg, cap)) / (2 * eps)
+    assert np.max(np.abs(dp - fd)) <= 1e-8 * np.max(np.abs(fd))
+    # dU is orthogonal to the kept subspace (a rotation inside it cancels)
+    assert np.max(np.abs(u.T @ du)) <= 1e-13
+
+
+def test_isometry_derivative_leaves_out_pairs_closer_than_1e12():
+    d1, d2, cap = 2, 4, 4
+    lam = [1.0, 0.5, 0.2, 3e-13, 2e-13, 0.0, 0.0, 0.0]   # kept 4; the cut pair 1e-13 apart
+    g, w = _gram(lam, 6)
+    rng = np.random.default_rng(7)
+    dg = rng.standard_normal((8, 8))
+    dg = dg + dg.T
+    prm = trg.Params(D=cap, tau_deg=0.0)
+    u = trg.triad_isometry(g, d1, d2, cap, prm, "t", {})
+    du = impurity._iso_tangent(g, dg, d1, d2, cap, prm).reshape(8, cap)
+    lam_c, w_c = trg.jacobi_eigh(g)
+    assert trg.kept_count(lam_c, cap, prm.eps_lam, prm.tau_deg) == 4
+    w4 = w_c[:, 4]   # the discarded partner of the smallest kept value
+    # no rotation between the pair: u_3 does not move along w_4
+    assert abs(w4 @ du[:, 3]) <= 1e-12 * np.max(np.abs(du))
+    # a separated pair keeps the first-order coefficient
+    i0 = int(np.argmax(np.abs(u.T @ w_c[:, 0])))   # the column of u along the top eigenvector
+    coef = (w4 @ dg @ u[:, i0]) / (lam_c[0] - lam_c[4])
+    assert abs(w4 @ du[:, i0] - coef) <= 1e-10 * abs(coef)
