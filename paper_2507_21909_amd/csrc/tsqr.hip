@@ -19,14 +19,14 @@
 namespace trg {
 
 namespace {
-constexpr int NT = 256;
 constexpr int RB = 256;   // rows per block
 
 // Block factorisation with the block's columns spread over the workgroup: a
 // group of TPC = NTH / NC adjacent lanes owns column c, lane q of the group
 // holding rows TPC i + q (i < RPT = 256 / TPC) in registers, so every dot
-// product of a column with the reflector is RPT fused multiply-adds in a lane
-// and a log2(TPC)-step butterfly inside the group.  Step j: the lanes of
+// product of a column with the reflector is RPT products summed pairwise in a
+// lane and a log2(TPC)-step butterfly inside the group (the depth of a tree
+// over the block's 256 rows).  Step j: the lanes of
 // column j form the reflector (norm by the same butterfly) and write it, zero
 // above row j, to LDS; after one barrier every column right of j reads it
 // there and updates itself, and the workgroup copies it, one row a thread,
