@@ -155,8 +155,10 @@ int gu_wen_x(trg_state *s, int axis, double *out);
  * of the site tensor, summed over the sites, is carried through every step:
  * the re-split and bond-swap tangents taken in the tangent space of the
  * rank-chi matrices, the triad isometries' kept subspaces moved with their
- * Grams (first-order invariant-subspace perturbation), the squeezers and
- * norms held; then d(log Z/V) = 2^-n Tr dT^(n) / Tr T^(n).  Exact where
+ * Grams (first-order invariant-subspace perturbation; kept / discarded pairs
+ * whose eigenvalues differ by at most 1e-12 of the largest are treated as
+ * degenerate and not rotated), the squeezers and norms held; then
+ * d(log Z/V) = 2^-n Tr dT^(n) / Tr T^(n).  Exact where
  * nothing is truncated; otherwise it differs from the derivative of the
  * truncated flow by what the held squeezers and the bond swap's tangent-space
  * form leave out (about 4e-4 relative at D = 8 near T_c).  The internal
