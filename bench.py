@@ -234,7 +234,7 @@ def main():
                     help="time steps replayed from HIP graphs recorded after the warmup (no kernel timing)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the RG step on a single MI355X "
+        print("bench.py measures one GPU: the library runs the RG step on a single MI355X "
               "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

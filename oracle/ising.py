@@ -2,7 +2,7 @@
 
 Test infrastructure only.
 
-Model (Sec. III): H = -sum_<ij> s_i s_j with s = +-1; this build adds a site
+Model (Sec. III): H = -sum_<ij> s_i s_j with s = +-1; here with a site
 field, Z = sum_s exp(beta sum_{n,mu} s_n s_{n+mu} + h sum_n s_n) on a periodic
 torus.  The field enters the site tensor as exp(h s) (no factor beta).
 
