@@ -70,3 +70,21 @@ def test_graph_and_batch_entry_points_reject_bad_arguments(lib_path):
     assert lib.trg_batch_run_graphs(None, 4, None) == -1
     assert lib.trg_batch_run(None, 4, None) == -1
     assert lib.trg_strerror(-7).decode().startswith("truncation cut inside a multiplet")
+
+
+def test_selftest_entry_points_reject_bad_arguments(lib_path):
+    import ctypes
+    from paper_2507_21909_amd import binding
+    lib = binding.load_library(lib_path)
+    ip = lambda *v: (ctypes.c_int * len(v))(*v)
+    buf = (ctypes.c_double * 8)()
+    dp = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+    # the permute check runs before any device call: rank, sizes, a true permutation
+    assert lib.trg_selftest_permute(0, ip(2), ip(0), dp, dp) == -1
+    assert lib.trg_selftest_permute(9, ip(*[1] * 9), ip(*range(9)), dp, dp) == -1
+    assert lib.trg_selftest_permute(2, ip(2, 0), ip(1, 0), dp, dp) == -1
+    assert lib.trg_selftest_permute(2, ip(2, 3), ip(0, 0), dp, dp) == -1
+    assert lib.trg_selftest_permute(2, ip(2, 3), ip(0, 2), dp, dp) == -1
+    assert lib.trg_selftest_permute(2, None, ip(1, 0), dp, dp) == -1
+    assert lib.trg_selftest_tsqr(5, 6, dp, dp, dp) == -1      # m < n
+    assert lib.trg_selftest_tsqr(6, 0, dp, dp, dp) == -1
