@@ -126,11 +126,6 @@ __global__ void inv_pos_kernel(const double *v, double *out, int n) {
     if (j < n) out[j] = v[j] > 0.0 ? 1.0 / v[j] : 0.0;
 }
 
-__global__ void mask_sign_kernel(double *sg, const double *s, int n) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n && !(s[j] > 0.0)) sg[j] = 0.0;
-}
-
 // out[j] = sqrt(lam[j]) if lam[j] > eps * lam[0] else 0
 __global__ void sqrt_clamp_kernel(const double *lam, double *out, int n, double eps) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
